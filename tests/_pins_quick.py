@@ -1,0 +1,48 @@
+"""Run a quick subset of the oracle pins; exit 1 on the first failure.
+
+Used by the mutation test: a copy of the oracle with one planted mistake is
+loaded through ORACLE_LIB, and some pin here must fail."""
+import json
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import oracle                                   # noqa: E402
+from oracle.brute import brute_mincut           # noqa: E402
+from workloads import random_graph              # noqa: E402
+from tests._graphs import graph_from_json, path_graph   # noqa: E402
+
+
+def main():
+    try:
+        for seed in range(40):
+            n = 4 + seed % 10
+            g = random_graph(n, 3 * n, seed)
+            best = brute_mincut(g)[0]
+            for res in (oracle.fifo_maxflow(g), oracle.sync_maxflow(g)):
+                if res["value"] != best:
+                    return 1
+                if oracle.check_certificate(g, res["flow"], res["tstar"])[0] != 0:
+                    return 1
+        g = path_graph([6] * 13)
+        B = oracle.sync_maxflow(g)
+        if B["rounds"] != 12 or B["relabels"] != 0:
+            return 1
+        gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                           "prsn_two_vertex_trace.json")))
+        g = graph_from_json(gold["graph"])
+        r1 = oracle.sync_maxflow(g, preflow_only=True, max_rounds=1)
+        if r1["res"].tolist() != gold["after_round_1"]["res"] or r1["d"].tolist() != gold["after_round_1"]["d"]:
+            return 1
+        full = oracle.sync_maxflow(g)
+        if full["flow"].tolist() != gold["phase2"]["flow"]:
+            return 1
+    except Exception:
+        return 1
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
