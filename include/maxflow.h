@@ -1,0 +1,155 @@
+/*
+ * maxflow.h -- C ABI of the MI355X maximum-flow / minimum-cut library.
+ *
+ * The library computes a maximum s-t flow and a minimum cut with the
+ * synchronous parallel push-relabel method of Baumstark, Blelloch and Shun
+ * (Sec. 3.1: rounds that fully discharge every active vertex against the
+ * labels and excesses of the start of the round, settle conflicts between
+ * adjacent active vertices with the win criterion, and apply new labels and
+ * excess changes at the end of the round), interleaved with a parallel
+ * global relabel (Sec. 2.1, Sec. 3: reverse breadth-first search from the
+ * sink).  All arithmetic is exact integer arithmetic.
+ *
+ * Problem statement (Sec. 2, Eq. 1-2): directed graph G = (V, E) with
+ * capacities c(v,w) >= 0, source s and sink t, s != t.  A flow obeys
+ * f(v,w) <= c(v,w), conservation at every vertex other than s and t, and
+ * antisymmetry f(v,w) = -f(w,v).  Its value is the net flow into t.  A
+ * minimum cut (S, T) with s in S and t in T has capacity equal to the
+ * maximum flow value.
+ *
+ * Graph format: CSR with paired reverse slots (the adjacency arrays of
+ * Sec. 4.2 in which every edge knows its reverse edge).
+ *   offsets[n+1]  int64, slots of tail v are offsets[v] .. offsets[v+1]-1,
+ *                 offsets[0] = 0, non-decreasing, offsets[n] = slots
+ *   head[slots]   int32, head w of slot (v, w), 0 <= w < n, w != v
+ *   rev[slots]    int64, the paired reverse slot: rev[rev[a]] = a and
+ *                 head[rev[a]] = v; an arc given in one direction only is
+ *                 paired with a reverse slot of capacity 0
+ *   cap[slots]    int32, c(v, w) >= 0, and cap[a] + cap[rev[a]] < 2^31
+ * Limits: 2 <= n < 2^31, slots < 2^31 - 1.
+ *
+ * Outputs:
+ *   value         int64, maximum flow value (net flow into t)
+ *   flow[slots]   int32, flow[a] = cap[a] - residual[a]; flow[rev[a]] =
+ *                 -flow[a]; a maximum flow (Eq. 1-2 hold); maximum flows
+ *                 are not unique, so any valid one is correct
+ *   sink_side[n]  uint8, 1 iff v reaches t in the final residual graph
+ *                 (the smallest sink side T* of a minimum cut, which is
+ *                 unique); 0 for every other vertex
+ *   cut_capacity  int64, sum of cap[a] over slots from a vertex with
+ *                 sink_side 0 to one with sink_side 1; equals value
+ *
+ * Errors: every call returns an mf_status and never aborts the process.
+ * Ownership: the caller owns every buffer it passes; the library owns its
+ * device workspace, which lives in the context and is freed by
+ * mf_context_destroy.  A context serves one host thread at a time.
+ */
+#ifndef MI355X_MAXFLOW_H
+#define MI355X_MAXFLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MF_OK = 0,
+    MF_EINVAL = 1,     /* invalid argument or graph (see mf_last_error) */
+    MF_ENOMEM = 2,     /* the request exceeds the context's HBM budget or device memory */
+    MF_EDEVICE = 3,    /* a HIP call failed (see mf_last_error) */
+    MF_ETIMEOUT = 4,   /* max_rounds reached; outputs hold a valid preflow */
+    MF_EAGAIN = 5,     /* not finished yet (server poll) or no free slot */
+    MF_ECANCELED = 6,  /* request canceled */
+    MF_ENOTFOUND = 7   /* unknown ticket or handle */
+} mf_status;
+
+typedef struct {
+    int32_t n;
+    int64_t slots;
+    const int64_t *offsets;
+    const int32_t *head;
+    const int64_t *rev;
+    const int32_t *cap;
+    int32_t s, t;
+} mf_graph;
+
+/* flags */
+#define MF_PREFLOW_ONLY 0x1u   /* stop at the maximum preflow (Sec. 2.1); flow output not produced */
+
+typedef struct {
+    /* Global-relabel schedule (Sec. 3 and its footnote): a global relabel
+     * runs when gr_freq_num * W > gr_freq_den * (gr_alpha * n + slots), where
+     * W is the relabel work since the last one (each relabel of v adds
+     * outdeg(v) + gr_beta) plus gr_round_charge per round.  The paper's
+     * constants are freq = 1/2, alpha = 6, beta = 12 and no round charge. */
+    int64_t gr_freq_num, gr_freq_den, gr_alpha, gr_beta, gr_round_charge;
+    int64_t max_rounds;          /* 0 = unlimited; counts rounds of phase 1 */
+    uint32_t flags;
+    int32_t lanes_per_vertex;    /* lanes that discharge one vertex: 0 = automatic, else 1..64, power of 2 */
+    int32_t lanes_per_merge;     /* lanes that merge one vertex's excess: 0 = automatic */
+    int32_t reserved[5];
+} mf_options;
+
+typedef struct {
+    int64_t value, cut_capacity;
+    int64_t rounds, global_relabels, bfs_levels;        /* phase 1 */
+    int64_t rounds2, global_relabels2;                  /* phase 2 (flow reconstruction) */
+    int64_t pushes, relabels, arc_scans, work;          /* phase 1 counters */
+    double ms_preflow;   /* device time of phase 1 (init to maximum preflow) */
+    double ms_total;     /* device time of the whole solve, outputs included */
+} mf_stats;
+
+typedef struct mf_context mf_context;
+typedef struct mf_dgraph mf_dgraph;
+
+/* Fills *o with the paper's schedule (freq 1/2, alpha 6, beta 12, no round
+ * charge), no round limit, automatic lane counts. */
+void mf_options_default(mf_options *o);
+
+/* Library version string and the last error message of a context (or of the
+ * last context-free failure when ctx is NULL). */
+const char *mf_version(void);
+const char *mf_status_str(mf_status s);
+const char *mf_last_error(const mf_context *ctx);
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the context may hold (0 = no bound beyond the device's).
+ * The context owns one HIP stream on which it runs all its work. */
+mf_status mf_context_create(int device, size_t hbm_budget_bytes, mf_context **out);
+void mf_context_destroy(mf_context *ctx);
+
+/* Step 1 of a solve (residency and validation): copies the graph into
+ * library-owned device memory, narrows offsets and rev to int32 and checks
+ * it (rev is an involution with matching heads, heads in range, no
+ * self-loops, cap >= 0, pair sums below 2^31, s != t).  `g` holds host
+ * pointers when on_device = 0 and device pointers when on_device = 1 (then
+ * they must stay valid until this call returns).  Returns MF_EINVAL for an
+ * invalid graph, MF_ENOMEM beyond the budget. */
+mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_dgraph **out);
+void mf_graph_free(mf_context *ctx, mf_dgraph *dg);
+
+/* Solves an uploaded graph on the context's stream.  flow_dev (int32[slots])
+ * and side_dev (uint8[n]) are device pointers that receive the outputs, or
+ * NULL to skip them; flow_dev must be NULL with MF_PREFLOW_ONLY.  The call
+ * returns when the outputs are complete.  value / stats may be NULL. */
+mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt,
+                            int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
+                            mf_stats *stats);
+
+/* Upload + solve + copy-out for host buffers: flow (int32[slots]) and
+ * sink_side (uint8[n]) are host pointers or NULL. */
+mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_options *opt,
+                   int64_t *value, int32_t *flow, uint8_t *sink_side, mf_stats *stats);
+
+/* The same for a graph and outputs already in device memory (for example
+ * torch tensors); the call returns when the outputs are complete. */
+mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, const mf_options *opt,
+                          int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
+                          mf_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

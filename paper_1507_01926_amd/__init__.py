@@ -1,0 +1,237 @@
+"""Python binding of the MI355X maximum-flow library (libmaxflow.so).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+The binding raises ``RuntimeError`` if the built library is missing; there is
+no CPU fallback.  PyTorch, when used, only provides device buffers.
+
+The functions carry the names of the C ABI (``include/maxflow.h``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmaxflow.so")
+
+MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ETIMEOUT, MF_EAGAIN, MF_ECANCELED, MF_ENOTFOUND = range(8)
+STATUS_NAMES = {0: "MF_OK", 1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ETIMEOUT",
+                5: "MF_EAGAIN", 6: "MF_ECANCELED", 7: "MF_ENOTFOUND"}
+MF_PREFLOW_ONLY = 0x1
+
+
+class MaxflowError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mf_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("slots", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("head", ctypes.c_void_p),
+                ("rev", ctypes.c_void_p), ("cap", ctypes.c_void_p),
+                ("s", ctypes.c_int32), ("t", ctypes.c_int32)]
+
+
+class mf_options(ctypes.Structure):
+    _fields_ = [("gr_freq_num", ctypes.c_int64), ("gr_freq_den", ctypes.c_int64),
+                ("gr_alpha", ctypes.c_int64), ("gr_beta", ctypes.c_int64),
+                ("gr_round_charge", ctypes.c_int64), ("max_rounds", ctypes.c_int64),
+                ("flags", ctypes.c_uint32), ("lanes_per_vertex", ctypes.c_int32),
+                ("lanes_per_merge", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class mf_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "value", "cut_capacity", "rounds", "global_relabels", "bfs_levels", "rounds2",
+        "global_relabels2", "pushes", "relabels", "arc_scans", "work")] + [
+        ("ms_preflow", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+_LIB = None
+
+# (name, restype, argtypes) of every symbol include/maxflow.h declares
+_P = ctypes.c_void_p
+SIGNATURES = [
+    ("mf_options_default", None, [_P]),
+    ("mf_version", ctypes.c_char_p, []),
+    ("mf_status_str", ctypes.c_char_p, [ctypes.c_int]),
+    ("mf_last_error", ctypes.c_char_p, [_P]),
+    ("mf_context_create", ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, _P]),
+    ("mf_context_destroy", None, [_P]),
+    ("mf_graph_upload", ctypes.c_int, [_P, _P, ctypes.c_int, _P]),
+    ("mf_graph_free", None, [_P, _P]),
+    ("mf_solve_uploaded", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("mf_solve", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("mf_solve_device", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+]
+
+
+def lib():
+    """Load libmaxflow.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        # A process must hold one HIP runtime.  PyTorch ships its own copy; if
+        # it is importable, load it first so that libmaxflow.so binds to the
+        # same runtime (same soname) and torch device buffers can be passed in.
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_1507_01926_amd/build.py` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def mf_version() -> str:
+    return lib().mf_version().decode()
+
+
+def options(**kw) -> mf_options:
+    """mf_options with the paper's defaults, overridden by keyword."""
+    o = mf_options()
+    lib().mf_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "preflow_only":
+            o.flags = (o.flags | MF_PREFLOW_ONLY) if v else (o.flags & ~MF_PREFLOW_ONLY)
+        else:
+            setattr(o, k, int(v))
+    return o
+
+
+def _stats_dict(s: mf_stats) -> dict:
+    return {k: getattr(s, k) for k, _ in mf_stats._fields_}
+
+
+class _HostGraph:
+    """ctypes view of a host graph (numpy arrays kept alive)."""
+
+    def __init__(self, g):
+        self.off = np.ascontiguousarray(g.off, dtype=np.int64)
+        self.head = np.ascontiguousarray(g.head, dtype=np.int32)
+        self.rev = np.ascontiguousarray(g.rev, dtype=np.int64)
+        self.cap = np.ascontiguousarray(g.cap, dtype=np.int32)
+        self.st = mf_graph(int(g.n), int(self.head.shape[0]), self.off.ctypes.data,
+                           self.head.ctypes.data, self.rev.ctypes.data, self.cap.ctypes.data,
+                           int(g.s), int(g.t))
+
+
+class Context:
+    """An mf_context: one device, one HIP stream, an optional HBM budget."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        st = lib().mf_context_create(int(device), int(hbm_budget_bytes), ctypes.byref(h))
+        if st != MF_OK:
+            raise MaxflowError(st, lib().mf_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().mf_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st not in (MF_OK,):
+            raise MaxflowError(st, lib().mf_last_error(self.h).decode())
+
+    # -- mf_solve: host buffers in, host buffers out -----------------------
+    def solve(self, g, opt: mf_options | None = None, want_flow=True, want_side=True,
+              allow_timeout=False) -> dict:
+        hg = _HostGraph(g)
+        opt = opt or options()
+        if opt.flags & MF_PREFLOW_ONLY:
+            want_flow = False
+        flow = np.zeros(max(1, hg.head.shape[0]), dtype=np.int32) if want_flow else None
+        side = np.zeros(g.n, dtype=np.uint8) if want_side else None
+        val = ctypes.c_int64(0)
+        stats = mf_stats()
+        st = lib().mf_solve(self.h, ctypes.byref(hg.st), ctypes.byref(opt), ctypes.byref(val),
+                            None if flow is None else flow.ctypes.data,
+                            None if side is None else side.ctypes.data, ctypes.byref(stats))
+        if not (allow_timeout and st == MF_ETIMEOUT):
+            self._check(st)
+        out = _stats_dict(stats)
+        out.update(status=st, value=int(val.value), sink_side=side,
+                   flow=None if flow is None else flow[: hg.head.shape[0]])
+        return out
+
+    # -- upload once, solve many times (device-resident graph) -------------
+    def upload(self, g) -> "DeviceGraph":
+        hg = _HostGraph(g)
+        h = ctypes.c_void_p()
+        self._check(lib().mf_graph_upload(self.h, ctypes.byref(hg.st), 0, ctypes.byref(h)))
+        return DeviceGraph(self, h, g.n, hg.head.shape[0])
+
+    def upload_device(self, off, head, rev, cap, s, t) -> "DeviceGraph":
+        """Graph arrays given as device pointers (e.g. torch tensors on cuda)."""
+        n = int(off.numel()) - 1
+        S = int(head.numel())
+        gst = mf_graph(n, S, off.data_ptr(), head.data_ptr(), rev.data_ptr(), cap.data_ptr(),
+                       int(s), int(t))
+        h = ctypes.c_void_p()
+        self._check(lib().mf_graph_upload(self.h, ctypes.byref(gst), 1, ctypes.byref(h)))
+        return DeviceGraph(self, h, n, S)
+
+    def solve_device(self, off, head, rev, cap, s, t, flow=None, side=None,
+                     opt: mf_options | None = None) -> dict:
+        """mf_solve_device: inputs and outputs are device buffers (torch tensors)."""
+        n = int(off.numel()) - 1
+        S = int(head.numel())
+        gst = mf_graph(n, S, off.data_ptr(), head.data_ptr(), rev.data_ptr(), cap.data_ptr(),
+                       int(s), int(t))
+        val = ctypes.c_int64(0)
+        stats = mf_stats()
+        st = lib().mf_solve_device(self.h, ctypes.byref(gst), ctypes.byref(opt or options()),
+                                   ctypes.byref(val), None if flow is None else flow.data_ptr(),
+                                   None if side is None else side.data_ptr(), ctypes.byref(stats))
+        self._check(st)
+        out = _stats_dict(stats)
+        out.update(value=int(val.value))
+        return out
+
+
+class DeviceGraph:
+    """An mf_dgraph: a validated graph resident in the context's device memory."""
+
+    def __init__(self, ctx: Context, h, n: int, slots: int):
+        self.ctx, self.h, self.n, self.slots = ctx, h, n, slots
+
+    def free(self):
+        if self.h and self.ctx.h:
+            lib().mf_graph_free(self.ctx.h, self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def solve(self, opt: mf_options | None = None, flow_ptr=None, side_ptr=None,
+              allow_timeout=False) -> dict:
+        """mf_solve_uploaded; flow_ptr / side_ptr are device addresses or None."""
+        val = ctypes.c_int64(0)
+        stats = mf_stats()
+        st = lib().mf_solve_uploaded(self.ctx.h, self.h, ctypes.byref(opt or options()),
+                                     ctypes.byref(val), flow_ptr, side_ptr, ctypes.byref(stats))
+        if not (allow_timeout and st == MF_ETIMEOUT):
+            self.ctx._check(st)
+        out = _stats_dict(stats)
+        out.update(status=st, value=int(val.value))
+        return out

@@ -1,0 +1,142 @@
+// Device-side data layout and wave helpers shared by the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+// Library-owned device copy of a validated graph; int32 offsets and reverse
+// slots (the library requires slots < 2^31 - 1).
+struct GraphView {
+    int32_t n, s, t;
+    int32_t slots;
+    const int32_t *off;    // [n+1]
+    const int32_t *head;   // [slots]
+    const int32_t *rev;    // [slots]
+    const int32_t *cap;    // [slots]
+};
+
+// Counters written by the kernels and read back by the host driver.
+struct Ctl {
+    int32_t na;            // entries of the current working-set list
+    int32_t na2;           // entries appended to the next working-set list
+    int32_t nc;            // entries of the candidate list
+    int32_t nq[3];         // BFS frontier sizes, ring indexed by level % 3
+    int32_t err;           // validation error bits
+    int32_t pad;
+    int64_t work;          // relabel work of the round (sum of outdeg + beta)
+    int64_t pushes, relabels, scans;
+    int64_t cut;           // cut capacity accumulator
+    int64_t value;         // scratch for the host
+};
+
+// Per-solve state.  Every array lives in device memory.
+//   res[a]    residual capacity of slot a as of the last round end
+//   delta[a]  push received on slot a during the current round (a push on
+//             slot b by head[a] is stored at a = rev[b]); 0 outside rounds
+//   d[v]      label at the start of the round; dn[v] label after v's discharge
+//   e[v]      excess; act[v] 1 iff v is in the working set
+//   owner[w]  index of the candidate-list entry that merges w this round
+struct StateView {
+    int32_t *res, *delta, *d, *dn, *owner;
+    int64_t *e;
+    uint8_t *act;
+    int32_t *A, *A2;       // working-set lists (current, next)
+    int32_t *C;            // candidate list (vertices touched in the round)
+    int32_t *Q, *Q2;       // BFS frontiers
+    Ctl *ctl;
+};
+
+// ---------------------------------------------------------------------------
+// Wave helpers (wave64).  A "group" is G consecutive lanes of a wave that
+// cooperate on one vertex; G divides 64.
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <int G>
+__device__ __forceinline__ int64_t group_incl_scan(int64_t x, int gl)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        int64_t y = __shfl_up(x, (unsigned)o, G);
+        if (gl >= o) x += y;
+    }
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ int64_t group_bcast(int64_t x, int src)
+{
+    return G == 1 ? x : __shfl(x, src, G);
+}
+
+template <int G>
+__device__ __forceinline__ int group_min(int x)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        int y = __shfl_xor(x, o, G);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ int64_t group_sum(int64_t x)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ int group_or(int x)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) x |= __shfl_xor(x, o, G);
+    return x;
+}
+
+// Appends `val` for every calling lane with `pred` set to list[*count ...]
+// with one atomic per wave: ballot, then each lane's rank among the set
+// lanes below it.  Returns the slot index of the lane's entry (or -1).
+__device__ __forceinline__ int wave_append(bool pred, int32_t val, int32_t *list, int32_t *count)
+{
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return -1;
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(count, (int32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    int idx = -1;
+    if (pred) {
+        idx = base + lanes_below(mask);
+        list[idx] = val;
+    }
+    return idx;
+}
+
+// Block-wide sum of a per-thread int64 into *dst with one atomic per block.
+__device__ __forceinline__ void block_add64(int64_t x, int64_t *dst)
+{
+    __shared__ int64_t part[16];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    int w = threadIdx.x >> 6;
+    if (lane_id() == 0) part[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) s += part[i];
+        if (s) atomicAdd((unsigned long long *)dst, (unsigned long long)s);
+    }
+    __syncthreads();
+}
+
+}  // namespace mf

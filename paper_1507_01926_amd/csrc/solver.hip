@@ -1,0 +1,661 @@
+// Host driver and C ABI of the maximum-flow library.
+//
+// The driver runs the synchronous push-relabel loop of Sec. 3.1 (Listing 1):
+//   - init and source saturation;
+//   - global relabel first (W = infinity) and whenever the relabel work since
+//     the last one crosses the threshold of Sec. 3 (freq * W > alpha*n + m);
+//     a global relabel rebuilds the working set from every vertex with
+//     positive excess and a label below n;
+//   - a round = discharge + merge;
+//   - the loop ends when a global relabel run at that point finds no active
+//     vertex, so the result is a maximum preflow (value = e(t)) and the
+//     labels are exact BFS distances: sink_side[v] = d(v) < n.
+// Phase 2 (flow reconstruction, Sec. 2.1 / Sec. 3) runs the same loop with s
+// as the sink and t excluded, returning every remaining excess to s.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/maxflow.h"
+#include "mf_device.h"
+
+namespace mf {
+void launch_discharge(int G, GraphView g, StateView st, int64_t beta, int sink, int grid, hipStream_t s);
+void launch_merge(int G, GraphView g, StateView st, int sink, int other, int grid, hipStream_t s);
+void launch_gr_level(int G, GraphView g, StateView st, int level, int sink, int other,
+                     const int32_t *qin, int32_t *qout, int grid, hipStream_t s);
+void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
+                   int64_t slots, Ctl *ctl, int grid, hipStream_t s);
+void launch_validate(GraphView g, Ctl *ctl, int grid, hipStream_t s);
+void launch_init_state(GraphView g, StateView st, int grid, hipStream_t s);
+void launch_saturate(GraphView g, StateView st, int grid, hipStream_t s);
+void launch_gr_init(GraphView g, StateView st, int sink, int grid, hipStream_t s);
+void launch_gr_rebuild(GraphView g, StateView st, int sink, int other, int grid, hipStream_t s);
+void launch_round_reset(Ctl *ctl, hipStream_t s);
+void launch_round_end(Ctl *ctl, hipStream_t s);
+void launch_side(GraphView g, const int32_t *d, uint8_t *side, int grid, hipStream_t s);
+void launch_cut(GraphView g, const uint8_t *side, Ctl *ctl, int grid, hipStream_t s);
+void launch_flow(GraphView g, const int32_t *res, int32_t *flow, int grid, hipStream_t s);
+void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s);
+}  // namespace mf
+
+using namespace mf;
+
+static thread_local std::string g_global_err;
+
+struct mf_dgraph {
+    int32_t n = 0, s = 0, t = 0;
+    int64_t slots = 0;
+    int32_t *off = nullptr, *head = nullptr, *rev = nullptr, *cap = nullptr;
+    size_t bytes = 0;
+    GraphView view() const
+    {
+        GraphView g;
+        g.n = n;
+        g.s = s;
+        g.t = t;
+        g.slots = (int32_t)slots;
+        g.off = off;
+        g.head = head;
+        g.rev = rev;
+        g.cap = cap;
+        return g;
+    }
+};
+
+struct Workspace {
+    int64_t n_cap = 0, s_cap = 0;
+    int32_t *res = nullptr, *delta = nullptr, *d = nullptr, *dn = nullptr, *owner = nullptr;
+    int64_t *e = nullptr;
+    uint8_t *act = nullptr, *side = nullptr;
+    int32_t *A = nullptr, *A2 = nullptr, *C = nullptr, *Q = nullptr, *Q2 = nullptr;
+    size_t bytes = 0;
+};
+
+struct mf_context {
+    int device = 0;
+    size_t budget = 0;     // 0 = unbounded
+    size_t used = 0;       // bytes held (graphs + workspace)
+    hipStream_t stream = nullptr;
+    Ctl *ctl = nullptr;        // device
+    Ctl *ctl_host = nullptr;   // pinned host mirror
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    Workspace ws;
+    int num_cus = 256;
+    std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// Error helpers
+
+static mf_status fail(mf_context *ctx, mf_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_global_err = buf;
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((ctx), MF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+static int grid_for(int64_t items, int per_block, int max_grid)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > max_grid) g = max_grid;
+    return (int)g;
+}
+
+static mf_status dalloc(mf_context *ctx, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 4;
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(ctx, MF_ENOMEM, "HBM budget exceeded: %zu held + %zu requested > %zu", ctx->used,
+                    bytes, ctx->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(ctx, MF_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    ctx->used += bytes;
+    return MF_OK;
+}
+
+static void dfree(mf_context *ctx, void *p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    if (bytes == 0) bytes = 4;
+    ctx->used -= std::min(ctx->used, bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Public helpers
+
+extern "C" {
+
+void mf_options_default(mf_options *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->gr_freq_num = 1;
+    o->gr_freq_den = 2;
+    o->gr_alpha = 6;
+    o->gr_beta = 12;
+    o->gr_round_charge = 0;
+    o->max_rounds = 0;
+    o->flags = 0;
+    o->lanes_per_vertex = 0;
+    o->lanes_per_merge = 0;
+}
+
+const char *mf_version(void) { return "mi355x-maxflow 0.1 (gfx950)"; }
+
+const char *mf_status_str(mf_status s)
+{
+    switch (s) {
+    case MF_OK: return "ok";
+    case MF_EINVAL: return "invalid argument";
+    case MF_ENOMEM: return "out of memory or over budget";
+    case MF_EDEVICE: return "device error";
+    case MF_ETIMEOUT: return "round limit reached";
+    case MF_EAGAIN: return "not ready";
+    case MF_ECANCELED: return "canceled";
+    case MF_ENOTFOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+const char *mf_last_error(const mf_context *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_global_err.c_str();
+}
+
+mf_status mf_context_create(int device, size_t hbm_budget_bytes, mf_context **out)
+{
+    if (!out) return fail(nullptr, MF_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0)
+        return fail(nullptr, MF_EDEVICE, "no HIP device available (%s)",
+                    e != hipSuccess ? hipGetErrorString(e) : "count 0");
+    if (device < 0 || device >= count)
+        return fail(nullptr, MF_EINVAL, "device %d out of range (%d devices)", device, count);
+    mf_context *ctx = new (std::nothrow) mf_context();
+    if (!ctx) return fail(nullptr, MF_ENOMEM, "host allocation failed");
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    mf_status st = MF_OK;
+    do {
+        if (hipSetDevice(device) != hipSuccess) { st = fail(nullptr, MF_EDEVICE, "hipSetDevice failed"); break; }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            st = fail(nullptr, MF_EDEVICE, "hipStreamCreate failed");
+            break;
+        }
+        if (hipMalloc((void **)&ctx->ctl, sizeof(Ctl)) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+            st = fail(nullptr, MF_EDEVICE, "control block allocation failed");
+            break;
+        }
+        for (auto &ev : ctx->ev)
+            if (hipEventCreate(&ev) != hipSuccess) { st = fail(nullptr, MF_EDEVICE, "hipEventCreate failed"); break; }
+    } while (0);
+    if (st != MF_OK) {
+        mf_context_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return MF_OK;
+}
+
+void mf_context_destroy(mf_context *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    Workspace &w = ctx->ws;
+    void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.A, w.A2, w.C, w.Q, w.Q2};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (ctx->ctl) (void)hipFree(ctx->ctl);
+    if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
+    for (auto ev : ctx->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Graph residency and validation (step a1)
+
+static const char *validation_message(int bits)
+{
+    if (bits & 1) return "offsets are not a non-decreasing sequence from 0 to slots";
+    if (bits & 2) return "a reverse slot index is out of range";
+    if (bits & 4) return "a head is out of range";
+    if (bits & 8) return "self-loop";
+    if (bits & 16) return "rev is not an involution with matching heads";
+    if (bits & 32) return "negative capacity";
+    if (bits & 64) return "cap[a] + cap[rev[a]] >= 2^31";
+    return "invalid graph";
+}
+
+static mf_status read_ctl(mf_context *ctx)
+{
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ctl_host, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MF_OK;
+}
+
+extern "C" mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_dgraph **out)
+{
+    if (!ctx || !g || !out) return fail(ctx, MF_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (g->n < 2) return fail(ctx, MF_EINVAL, "n must be at least 2");
+    if (g->slots < 0 || g->slots >= 2147483647LL || (int64_t)g->n + g->slots >= 2147483647LL)
+        return fail(ctx, MF_EINVAL, "slots out of the supported range");
+    if (g->s < 0 || g->s >= g->n || g->t < 0 || g->t >= g->n || g->s == g->t)
+        return fail(ctx, MF_EINVAL, "s and t must be distinct vertices");
+    if (!g->offsets || (g->slots > 0 && (!g->head || !g->rev || !g->cap)))
+        return fail(ctx, MF_EINVAL, "NULL graph array");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    mf_dgraph *dg = new (std::nothrow) mf_dgraph();
+    if (!dg) return fail(ctx, MF_ENOMEM, "host allocation failed");
+    dg->n = g->n;
+    dg->s = g->s;
+    dg->t = g->t;
+    dg->slots = g->slots;
+    const size_t S = (size_t)g->slots, N = (size_t)g->n;
+    dg->bytes = 4 * (N + 1) + 12 * S + 12;
+    mf_status st;
+    if ((st = dalloc(ctx, (void **)&dg->off, 4 * (N + 1))) != MF_OK ||
+        (st = dalloc(ctx, (void **)&dg->head, 4 * S)) != MF_OK ||
+        (st = dalloc(ctx, (void **)&dg->rev, 4 * S)) != MF_OK ||
+        (st = dalloc(ctx, (void **)&dg->cap, 4 * S)) != MF_OK) {
+        mf_graph_free(ctx, dg);
+        return st;
+    }
+    // int64 staging of offsets and rev, narrowed on the device
+    int64_t *off64 = nullptr, *rev64 = nullptr;
+    bool own64 = false;
+    if (on_device) {
+        off64 = const_cast<int64_t *>(g->offsets);
+        rev64 = const_cast<int64_t *>(g->rev);
+    } else {
+        own64 = true;
+        if ((st = dalloc(ctx, (void **)&off64, 8 * (N + 1))) != MF_OK ||
+            (st = dalloc(ctx, (void **)&rev64, 8 * S)) != MF_OK) {
+            dfree(ctx, off64, 8 * (N + 1));
+            mf_graph_free(ctx, dg);
+            return st;
+        }
+    }
+    auto cleanup = [&]() {
+        if (own64) {
+            dfree(ctx, off64, 8 * (N + 1));
+            dfree(ctx, rev64, 8 * S);
+        }
+    };
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t he = hipSuccess;
+    if (!on_device) {
+        he = hipMemcpyAsync(off64, g->offsets, 8 * (N + 1), hipMemcpyHostToDevice, ctx->stream);
+        if (he == hipSuccess && S) he = hipMemcpyAsync(rev64, g->rev, 8 * S, hipMemcpyHostToDevice, ctx->stream);
+    }
+    if (he == hipSuccess && S) he = hipMemcpyAsync(dg->head, g->head, 4 * S, kind, ctx->stream);
+    if (he == hipSuccess && S) he = hipMemcpyAsync(dg->cap, g->cap, 4 * S, kind, ctx->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream);
+    if (he != hipSuccess) {
+        cleanup();
+        mf_graph_free(ctx, dg);
+        return fail(ctx, MF_EDEVICE, "graph upload failed: %s", hipGetErrorString(he));
+    }
+    const int maxg = ctx->num_cus * 8;
+    launch_narrow(off64, rev64, dg->off, dg->rev, dg->n, dg->slots, ctx->ctl,
+                  grid_for(std::max<int64_t>(dg->slots, N + 1), 256, maxg), ctx->stream);
+    if ((st = read_ctl(ctx)) != MF_OK) {
+        cleanup();
+        mf_graph_free(ctx, dg);
+        return st;
+    }
+    if (ctx->ctl_host->err == 0) {
+        launch_validate(dg->view(), ctx->ctl, grid_for(S, 256, maxg), ctx->stream);
+        if ((st = read_ctl(ctx)) != MF_OK) {
+            cleanup();
+            mf_graph_free(ctx, dg);
+            return st;
+        }
+    }
+    cleanup();
+    if (ctx->ctl_host->err) {
+        int bits = ctx->ctl_host->err;
+        mf_graph_free(ctx, dg);
+        return fail(ctx, MF_EINVAL, "invalid graph: %s", validation_message(bits));
+    }
+    *out = dg;
+    return MF_OK;
+}
+
+extern "C" void mf_graph_free(mf_context *ctx, mf_dgraph *dg)
+{
+    if (!dg) return;
+    if (ctx) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        const size_t S = (size_t)dg->slots, N = (size_t)dg->n;
+        dfree(ctx, dg->off, 4 * (N + 1));
+        dfree(ctx, dg->head, 4 * S);
+        dfree(ctx, dg->rev, 4 * S);
+        dfree(ctx, dg->cap, 4 * S);
+    }
+    delete dg;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace
+
+static mf_status ensure_workspace(mf_context *ctx, int64_t n, int64_t slots)
+{
+    Workspace &w = ctx->ws;
+    if (w.n_cap >= n && w.s_cap >= slots && w.res) return MF_OK;
+    // release the old one
+    void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.A, w.A2, w.C, w.Q, w.Q2};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    ctx->used -= std::min(ctx->used, w.bytes);
+    w = Workspace();
+    const int64_t N = std::max(n, w.n_cap), S = std::max(slots, (int64_t)1);
+    mf_status st;
+    size_t before = ctx->used;
+    if ((st = dalloc(ctx, (void **)&w.res, 4 * S)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.delta, 4 * S)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.C, 4 * (S + N))) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.d, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.dn, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.owner, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.e, 8 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.act, N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.side, N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.A, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.A2, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.Q, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.Q2, 4 * N)) != MF_OK) return st;
+    w.n_cap = N;
+    w.s_cap = S;
+    w.bytes = ctx->used - before;
+    return MF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The solver
+
+struct PhaseStats {
+    int64_t rounds = 0, grs = 0, levels = 0;
+};
+
+static int pick_lanes(int requested, int64_t n, int64_t slots)
+{
+    if (requested > 0) {
+        int G = 1;
+        while (G < requested && G < 64) G <<= 1;
+        return G;
+    }
+    const double avg = n > 0 ? (double)slots / (double)n : 1.0;
+    int G = 1;
+    while (G < avg && G < 64) G <<= 1;
+    return std::max(G, 4);
+}
+
+struct Solve {
+    mf_context *ctx;
+    const mf_dgraph *dg;
+    GraphView g;
+    StateView st;
+    mf_options opt;
+    int G, Gm;
+    int maxgrid;
+    int64_t avg_deg_ceil;
+};
+
+static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, int &na)
+{
+    mf_context *ctx = S.ctx;
+    const int n = S.g.n;
+    launch_gr_init(S.g, S.st, sink, grid_for(n, 256, S.maxgrid), ctx->stream);
+    int nq = 1;
+    int level = 0;
+    int32_t *qin = S.st.Q, *qout = S.st.Q2;
+    while (nq > 0) {
+        const int groups = 256 / S.G;
+        launch_gr_level(S.G, S.g, S.st, level, sink, other, qin, qout, grid_for(nq, groups, S.maxgrid),
+                        ctx->stream);
+        mf_status st = read_ctl(ctx);
+        if (st != MF_OK) return st;
+        nq = ctx->ctl_host->nq[(level + 1) % 3];
+        std::swap(qin, qout);
+        level++;
+    }
+    ps.levels += level - 1;
+    ps.grs++;
+    launch_gr_rebuild(S.g, S.st, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream);
+    mf_status st = read_ctl(ctx);
+    if (st != MF_OK) return st;
+    na = ctx->ctl_host->na;
+    return MF_OK;
+}
+
+// One phase of the synchronous loop toward `sink`.  Returns MF_ETIMEOUT when
+// the round limit stops it.
+static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, PhaseStats &ps)
+{
+    mf_context *ctx = S.ctx;
+    const int64_t n = S.g.n, m = S.g.slots;
+    const mf_options &o = S.opt;
+    bool force = true;
+    int64_t W = 0;
+    int na = 0;
+    while (true) {
+        bool just = false;
+        if (force || o.gr_freq_num * W > o.gr_freq_den * (o.gr_alpha * n + m)) {
+            mf_status st = global_relabel(S, sink, other, ps, na);
+            if (st != MF_OK) return st;
+            W = 0;
+            force = false;
+            just = true;
+        }
+        if (na == 0) {
+            if (just) return MF_OK;
+            force = true;
+            continue;
+        }
+        if (max_rounds > 0 && ps.rounds >= max_rounds) return MF_ETIMEOUT;
+        launch_round_reset(ctx->ctl, ctx->stream);
+        const int groups = 256 / S.G;
+        launch_discharge(S.G, S.g, S.st, o.gr_beta, sink, grid_for(na, groups, S.maxgrid), ctx->stream);
+        const int64_t cand_bound = (int64_t)na * (1 + S.avg_deg_ceil);
+        launch_merge(S.Gm, S.g, S.st, sink, other, grid_for(cand_bound, 256 / S.Gm, S.maxgrid), ctx->stream);
+        launch_round_end(ctx->ctl, ctx->stream);
+        mf_status st = read_ctl(ctx);
+        if (st != MF_OK) return st;
+        W += ctx->ctl_host->work + o.gr_round_charge;
+        na = ctx->ctl_host->na;
+        std::swap(S.st.A, S.st.A2);
+        ps.rounds++;
+    }
+}
+
+static mf_status check_options(mf_context *ctx, const mf_options *o)
+{
+    if (o->gr_freq_den <= 0 || o->gr_freq_num < 0 || o->gr_alpha < 0 || o->gr_beta < 0 ||
+        o->gr_round_charge < 0 || o->max_rounds < 0)
+        return fail(ctx, MF_EINVAL, "invalid global-relabel schedule");
+    if (o->lanes_per_vertex < 0 || o->lanes_per_vertex > 64 || o->lanes_per_merge < 0 ||
+        o->lanes_per_merge > 64)
+        return fail(ctx, MF_EINVAL, "lane counts must be 0..64");
+    return MF_OK;
+}
+
+extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt,
+                                       int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
+                                       mf_stats *stats)
+{
+    if (!ctx || !dg) return fail(ctx, MF_EINVAL, "NULL context or graph");
+    mf_options o;
+    if (opt)
+        o = *opt;
+    else
+        mf_options_default(&o);
+    mf_status st = check_options(ctx, &o);
+    if (st != MF_OK) return st;
+    const bool preflow_only = (o.flags & MF_PREFLOW_ONLY) != 0;
+    if (preflow_only && flow_dev) return fail(ctx, MF_EINVAL, "flow output requires phase 2");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((st = ensure_workspace(ctx, dg->n, dg->slots)) != MF_OK) return st;
+
+    Solve S;
+    S.ctx = ctx;
+    S.dg = dg;
+    S.g = dg->view();
+    Workspace &w = ctx->ws;
+    S.st.res = w.res;
+    S.st.delta = w.delta;
+    S.st.d = w.d;
+    S.st.dn = w.dn;
+    S.st.owner = w.owner;
+    S.st.e = w.e;
+    S.st.act = w.act;
+    S.st.A = w.A;
+    S.st.A2 = w.A2;
+    S.st.C = w.C;
+    S.st.Q = w.Q;
+    S.st.Q2 = w.Q2;
+    S.st.ctl = ctx->ctl;
+    S.opt = o;
+    S.G = pick_lanes(o.lanes_per_vertex, dg->n, dg->slots);
+    S.Gm = o.lanes_per_merge > 0 ? pick_lanes(o.lanes_per_merge, 1, 1) : S.G;
+    S.maxgrid = ctx->num_cus * 16;
+    S.avg_deg_ceil = (dg->slots + dg->n - 1) / std::max<int64_t>(1, dg->n);
+
+    const int n = dg->n;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
+    launch_init_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
+    launch_saturate(S.g, S.st, ctx->num_cus * 4, ctx->stream);
+    launch_merge(S.Gm, S.g, S.st, dg->t, dg->s, ctx->num_cus * 4, ctx->stream);
+
+    PhaseStats p1;
+    mf_status ph = run_phase(S, dg->t, dg->s, o.max_rounds, p1);
+    if (ph != MF_OK && ph != MF_ETIMEOUT) return ph;
+    const bool timed_out = ph == MF_ETIMEOUT;
+    HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    if ((st = read_ctl(ctx)) != MF_OK) return st;
+    const int64_t pushes = ctx->ctl_host->pushes, relabels = ctx->ctl_host->relabels,
+                  scans = ctx->ctl_host->scans;
+
+    // value, sink side and cut capacity of the maximum preflow (the labels are
+    // exact distances to t here)
+    launch_read_value(w.e, dg->t, ctx->ctl, ctx->stream);
+    uint8_t *side = side_dev ? side_dev : w.side;
+    launch_side(S.g, w.d, side, grid_for(n, 256, S.maxgrid), ctx->stream);
+    HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->cut, 0, sizeof(int64_t), ctx->stream));
+    launch_cut(S.g, side, ctx->ctl, grid_for(dg->slots, 256, S.maxgrid), ctx->stream);
+    if ((st = read_ctl(ctx)) != MF_OK) return st;
+    const int64_t val = ctx->ctl_host->value, cut = ctx->ctl_host->cut;
+
+    PhaseStats p2;
+    if (!preflow_only && !timed_out) {
+        ph = run_phase(S, dg->s, dg->t, 0, p2);
+        if (ph != MF_OK) return ph;
+    }
+    if (flow_dev) launch_flow(S.g, w.res, flow_dev, grid_for(dg->slots, 256, S.maxgrid), ctx->stream);
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipGetLastError());
+
+    if (value) *value = val;
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->value = val;
+        stats->cut_capacity = cut;
+        stats->rounds = p1.rounds;
+        stats->global_relabels = p1.grs;
+        stats->bfs_levels = p1.levels;
+        stats->rounds2 = p2.rounds;
+        stats->global_relabels2 = p2.grs;
+        stats->pushes = pushes;
+        stats->relabels = relabels;
+        stats->arc_scans = scans;
+        float ms1 = 0, ms2 = 0;
+        (void)hipEventElapsedTime(&ms1, ctx->ev[0], ctx->ev[1]);
+        (void)hipEventElapsedTime(&ms2, ctx->ev[0], ctx->ev[2]);
+        stats->ms_preflow = ms1;
+        stats->ms_total = ms2;
+    }
+    return timed_out ? fail(ctx, MF_ETIMEOUT, "round limit %lld reached", (long long)o.max_rounds) : MF_OK;
+}
+
+extern "C" mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, const mf_options *opt,
+                                     int64_t *value, int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats)
+{
+    mf_dgraph *dg = nullptr;
+    mf_status st = mf_graph_upload(ctx, dev_g, 1, &dg);
+    if (st != MF_OK) return st;
+    st = mf_solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats);
+    mf_graph_free(ctx, dg);
+    return st;
+}
+
+extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_options *opt,
+                              int64_t *value, int32_t *flow, uint8_t *sink_side, mf_stats *stats)
+{
+    if (!ctx || !host_g) return fail(ctx, MF_EINVAL, "NULL argument");
+    mf_dgraph *dg = nullptr;
+    mf_status st = mf_graph_upload(ctx, host_g, 0, &dg);
+    if (st != MF_OK) return st;
+    int32_t *flow_dev = nullptr;
+    uint8_t *side_dev = nullptr;
+    const size_t S = (size_t)dg->slots, N = (size_t)dg->n;
+    if (flow && (st = dalloc(ctx, (void **)&flow_dev, 4 * S)) != MF_OK) {
+        mf_graph_free(ctx, dg);
+        return st;
+    }
+    if (sink_side && (st = dalloc(ctx, (void **)&side_dev, N)) != MF_OK) {
+        dfree(ctx, flow_dev, 4 * S);
+        mf_graph_free(ctx, dg);
+        return st;
+    }
+    st = mf_solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats);
+    if (st == MF_OK || st == MF_ETIMEOUT) {
+        hipError_t e = hipSuccess;
+        if (flow && S) e = hipMemcpy(flow, flow_dev, 4 * S, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && sink_side) e = hipMemcpy(sink_side, side_dev, N, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = fail(ctx, MF_EDEVICE, "result copy failed: %s", hipGetErrorString(e));
+    }
+    dfree(ctx, flow_dev, 4 * S);
+    dfree(ctx, side_dev, N);
+    mf_graph_free(ctx, dg);
+    return st;
+}
