@@ -77,6 +77,8 @@ typedef struct {
 
 /* flags */
 #define MF_PREFLOW_ONLY 0x1u   /* stop at the maximum preflow (Sec. 2.1); flow output not produced */
+#define MF_PROFILE      0x2u   /* time the discharge, merge and global-relabel kernels with HIP
+                                  events on the context's stream and count their algorithmic bytes */
 
 typedef struct {
     /* Global-relabel schedule (Sec. 3 and its footnote): a global relabel
@@ -99,6 +101,12 @@ typedef struct {
     int64_t pushes, relabels, arc_scans, work;          /* phase 1 counters */
     double ms_preflow;   /* device time of phase 1 (init to maximum preflow) */
     double ms_total;     /* device time of the whole solve, outputs included */
+    /* filled with MF_PROFILE (both phases): summed kernel durations, launch
+     * counts and algorithmic bytes (the bytes the method must move, by the
+     * per-unit model of the design notes) */
+    double ms_discharge, ms_merge, ms_global_relabel;
+    int64_t discharge_launches, merge_launches, global_relabel_launches;
+    int64_t discharge_bytes, merge_bytes, global_relabel_bytes;
 } mf_stats;
 
 typedef struct mf_context mf_context;

@@ -20,6 +20,7 @@ MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ETIMEOUT, MF_EAGAIN, MF_ECANCELED, M
 STATUS_NAMES = {0: "MF_OK", 1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ETIMEOUT",
                 5: "MF_EAGAIN", 6: "MF_ECANCELED", 7: "MF_ENOTFOUND"}
 MF_PREFLOW_ONLY = 0x1
+MF_PROFILE = 0x2
 
 
 class MaxflowError(RuntimeError):
@@ -47,7 +48,11 @@ class mf_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "value", "cut_capacity", "rounds", "global_relabels", "bfs_levels", "rounds2",
         "global_relabels2", "pushes", "relabels", "arc_scans", "work")] + [
-        ("ms_preflow", ctypes.c_double), ("ms_total", ctypes.c_double)]
+        ("ms_preflow", ctypes.c_double), ("ms_total", ctypes.c_double),
+        ("ms_discharge", ctypes.c_double), ("ms_merge", ctypes.c_double),
+        ("ms_global_relabel", ctypes.c_double)] + [(k, ctypes.c_int64) for k in (
+        "discharge_launches", "merge_launches", "global_relabel_launches", "discharge_bytes",
+        "merge_bytes", "global_relabel_bytes")]
 
 
 _LIB = None
@@ -103,6 +108,8 @@ def options(**kw) -> mf_options:
     for k, v in kw.items():
         if k == "preflow_only":
             o.flags = (o.flags | MF_PREFLOW_ONLY) if v else (o.flags & ~MF_PREFLOW_ONLY)
+        elif k == "profile":
+            o.flags = (o.flags | MF_PROFILE) if v else (o.flags & ~MF_PROFILE)
         else:
             setattr(o, k, int(v))
     return o

@@ -100,35 +100,46 @@ __global__ void k_init_state(GraphView g, StateView st)
         st.dn[v] = lab;
         st.e[v] = 0;
         st.act[v] = 0;
+        st.touched[v] = 0;
     }
 }
 
+// Saturation of the arcs out of s, written like a dense round: the heads
+// receive the capacity in delta[] of the reverse slot and are marked touched;
+// an arc into t goes straight to t (see chunk_pass).
 __global__ void k_saturate(GraphView g, StateView st)
 {
     const int beg = g.off[g.s], end = g.off[g.s + 1];
-    for (int base = beg + blockIdx.x * blockDim.x; base < end; base += gridDim.x * blockDim.x) {
-        const int a = base + threadIdx.x;
-        bool p = false;
-        int w = 0;
-        if (a < end) {
-            const int c = g.cap[a];
-            if (c > 0) {
-                p = true;
-                w = g.head[a];
-                st.res[a] = 0;
-                st.delta[g.rev[a]] = c;
-            }
+    int64_t to_sink = 0;
+    for (int a = beg + blockIdx.x * blockDim.x + threadIdx.x; a < end; a += gridDim.x * blockDim.x) {
+        const int c = g.cap[a];
+        if (c <= 0) continue;
+        const int w = g.head[a];
+        st.res[a] = 0;
+        if (w == g.t) {
+            st.res[g.rev[a]] += c;
+            to_sink += c;
+        } else {
+            st.delta[g.rev[a]] = c;
+            st.touched[w] = 1;
         }
-        const int idx = wave_append(p, w, st.C, &st.ctl->nc);
-        if (p) st.owner[w] = idx;
     }
+    block_add64(to_sink, &st.e[g.t]);
 }
 
 // ---------------------------------------------------------------------------
-// Global relabel: d(v) = n for all v, d(sink) = 0, then one kernel per BFS
-// level.  A frontier vertex v at level L claims every w != sink, other with a
-// residual arc w -> v (residual capacity of the reverse slot, c_f(w,v) > 0)
-// and d(w) = n by compare-and-swap, as in Listing 2.
+// Global relabel (Listing 2): d(v) = n for all v, d(sink) = 0, then one
+// breadth-first level at a time.  w gets label L+1 when it has a residual arc
+// w -> v into a vertex v of label L (c_f(w,v) > 0: the residual capacity of
+// the reverse slot) and w is neither terminal.  A level runs either
+//   top-down   over a list of the frontier: each frontier vertex claims its
+//              unlabelled neighbours by compare-and-swap (as in Listing 2);
+//              frontier vertices of degree above a threshold are put on a
+//              hub list and expanded by the whole grid (k_gr_hub), or
+//   bottom-up  over all vertices: every unlabelled vertex looks for a
+//              neighbour of label L through its own residual slots (no
+//              atomics; each vertex writes only its own label).
+// Both give the same labels: exact distances are unique.
 
 __global__ void k_gr_init(GraphView g, StateView st, int sink)
 {
@@ -143,23 +154,36 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
         st.ctl->nq[0] = 1;
         st.ctl->nq[1] = 0;
         st.ctl->nq[2] = 0;
+        st.ctl->nh[0] = 0;
+        st.ctl->nh[1] = 0;
+        st.ctl->nh[2] = 0;
         st.ctl->na = 0;
+        st.ctl->na2 = 0;
     }
 }
 
 template <int G>
-__global__ __launch_bounds__(256) void k_gr_level(GraphView g, StateView st, int level, int sink,
-                                                  int other, const int32_t *__restrict__ qin,
-                                                  int32_t *__restrict__ qout)
+__global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int level, int sink,
+                                               int other, const int32_t *__restrict__ qin,
+                                               int32_t *__restrict__ qout, int hubdeg)
 {
     const int nq = st.ctl->nq[level % 3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->nq[(level + 2) % 3] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.ctl->nq[(level + 2) % 3] = 0;
+        st.ctl->nh[(level + 1) % 3] = 0;
+    }
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
     const int next = level + 1;
+    int64_t gslots = 0;
     for (int i = blockIdx.x * groups + threadIdx.x / G; i < nq; i += gridDim.x * groups) {
         const int v = qin[i];
         const int beg = g.off[v], end = g.off[v + 1];
+        if (end - beg > hubdeg) {
+            wave_append(gl == 0, v, st.H, &st.ctl->nh[level % 3]);
+            continue;
+        }
+        if (gl == 0) gslots += end - beg;
         for (int base = beg; base < end; base += G) {
             const int a = base + gl;
             bool claim = false;
@@ -176,25 +200,106 @@ __global__ __launch_bounds__(256) void k_gr_level(GraphView g, StateView st, int
             wave_append(claim, w, qout, &st.ctl->nq[next % 3]);
         }
     }
+    block_add64(gslots, &st.ctl->gslots);
 }
 
-// Working set after a global relabel: every vertex other than the two
-// terminals with positive excess and a label below n.
-__global__ void k_gr_rebuild(GraphView g, StateView st, int sink, int other)
+// The hub vertices of a top-down level, each expanded by every block.
+__global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int level, int sink,
+                                                int other, int32_t *__restrict__ qout)
+{
+    const int nh = st.ctl->nh[level % 3];
+    const int next = level + 1;
+    int64_t gslots = 0;
+    for (int h = 0; h < nh; h++) {
+        const int v = st.H[h];
+        const int beg = g.off[v], end = g.off[v + 1];
+        if (blockIdx.x == 0 && threadIdx.x == 0) gslots += end - beg;
+        for (int base = beg + blockIdx.x * blockDim.x; base < end; base += gridDim.x * blockDim.x) {
+            const int a = base + threadIdx.x;
+            bool claim = false;
+            int w = 0;
+            if (a < end) {
+                w = g.head[a];
+                if (w != sink && w != other && st.d[w] == g.n && st.res[g.rev[a]] > 0) {
+                    if (atomicCAS(&st.d[w], g.n, next) == g.n) {
+                        claim = true;
+                        st.dn[w] = next;
+                    }
+                }
+            }
+            wave_append(claim, w, qout, &st.ctl->nq[next % 3]);
+        }
+    }
+    block_add64(gslots, &st.ctl->gslots);
+}
+
+__global__ __launch_bounds__(256) void k_gr_bu(GraphView g, StateView st, int level, int sink, int other)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.ctl->nq[(level + 2) % 3] = 0;
+        st.ctl->nh[(level + 1) % 3] = 0;
+    }
+    const int next = level + 1;
+    int found = 0;
+    int64_t gslots = 0;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < g.n; w += gridDim.x * blockDim.x) {
+        if (st.d[w] != g.n || w == sink || w == other) continue;
+        const int beg = g.off[w], end = g.off[w + 1];
+        for (int a = beg; a < end; a++) {
+            gslots++;
+            if (st.res[a] > 0 && st.d[g.head[a]] == level) {
+                st.d[w] = next;
+                st.dn[w] = next;
+                found++;
+                break;
+            }
+        }
+    }
+    block_add32(found, &st.ctl->nq[next % 3]);
+    block_add64(gslots, &st.ctl->gslots);
+}
+
+// Frontier list of a level from the labels (after a bottom-up level).
+__global__ void k_gr_collect(GraphView g, StateView st, int level, int32_t *__restrict__ qout)
 {
     for (int base = blockIdx.x * blockDim.x; base < g.n; base += gridDim.x * blockDim.x) {
         const int v = base + threadIdx.x;
-        bool p = false;
-        if (v < g.n) {
-            p = v != sink && v != other && st.e[v] > 0 && st.d[v] < g.n;
-            st.act[v] = p;
-        }
+        const bool p = v < g.n && st.d[v] == level;
+        wave_append(p, v, qout, &st.ctl->nq[(level + 2) % 3]);
+    }
+}
+
+// Working set after a global relabel: every vertex other than the two
+// terminals with positive excess and a label below n (dense flags + count).
+__global__ void k_gr_rebuild(GraphView g, StateView st, int sink, int other)
+{
+    int cnt = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const bool p = v != sink && v != other && st.e[v] > 0 && st.d[v] < g.n;
+        st.act[v] = p;
+        cnt += p;
+    }
+    block_add32(cnt, &st.ctl->na2);
+}
+
+// Working-set list from the activity flags.
+__global__ void k_compact_act(GraphView g, StateView st)
+{
+    for (int base = blockIdx.x * blockDim.x; base < g.n; base += gridDim.x * blockDim.x) {
+        const int v = base + threadIdx.x;
+        const bool p = v < g.n && st.act[v];
         wave_append(p, v, st.A, &st.ctl->na);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Discharge (Listing 1, the loop over the working set).
+//
+// A round runs in one of two modes.  In list mode the working set is the list
+// A and every touched vertex is appended to the candidate list C, with
+// owner[w] naming one entry per vertex.  In dense mode (large working sets)
+// the kernels walk all vertices: the working set is act[], and touched[]
+// marks the vertices to merge, which avoids list appends altogether.
 
 struct RoundParams {
     int64_t beta;      // work per relabel = outdeg + beta
@@ -210,7 +315,7 @@ struct RoundParams {
 // The sink never discharges and nobody reads its own slots or its excess
 // during a round, so a push into the sink updates the reverse slot directly
 // (each slot has one pusher) and is added to the sink's excess once per block.
-template <int G>
+template <int G, bool DENSE>
 __device__ __forceinline__ int chunk_pass(const GraphView &g, StateView &st, int v, int dv, int dp,
                                           int gl, int a, int &r, int w, int dw, bool aw,
                                           int64_t &el, bool &lose, int64_t &pushes, int sink,
@@ -238,26 +343,39 @@ __device__ __forceinline__ int chunk_pass(const GraphView &g, StateView &st, int
             to_sink += dl;
         } else {
             st.delta[g.rev[a]] = dl;
+            if (DENSE) st.touched[w] = 1;
         }
     }
-    const bool app = dl > 0 && !into_sink;
-    const int idx = wave_append(app, w, st.C, &st.ctl->nc);
-    if (app) st.owner[w] = idx;
+    if (!DENSE) {
+        const bool app = dl > 0 && !into_sink;
+        const int idx = wave_append(app, w, st.C, &st.ctl->nc);
+        if (app) st.owner[w] = idx;
+    }
     el = tot >= el ? 0 : el - tot;
     return dl;
 }
 
-template <int G>
+template <int G, bool DENSE>
 __global__ __launch_bounds__(256) void k_discharge(GraphView g, StateView st, RoundParams p)
 {
-    const int na = st.ctl->na;
+    const int limit = DENSE ? g.n : st.ctl->na;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
     const int n = g.n;
-    int64_t work = 0, pushes = 0, relabels = 0, scans = 0, to_sink = 0;
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups) {
-        const int v = st.A[i];
+    int64_t work = 0, pushes = 0, relabels = 0, scans = 0, to_sink = 0, dverts = 0, dslots = 0;
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < limit; i += gridDim.x * groups) {
+        int v;
+        if (DENSE) {
+            v = i;
+            if (!st.act[v]) continue;
+        } else {
+            v = st.A[i];
+        }
         const int beg = g.off[v], end = g.off[v + 1], deg = end - beg;
+        if (gl == 0) {
+            dverts++;
+            dslots += deg;
+        }
         const int dv = st.d[v];
         int dp = dv;
         int64_t el = st.e[v];
@@ -278,7 +396,8 @@ __global__ __launch_bounds__(256) void k_discharge(GraphView g, StateView st, Ro
             while (el > 0) {
                 if (gl == 0) scans += deg;
                 bool lose;
-                if (chunk_pass<G>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, pushes, p.sink, to_sink) > 0)
+                if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, pushes, p.sink,
+                                         to_sink) > 0)
                     dirty = true;
                 if (el == 0) break;
                 const int cand = (r > 0 && dw >= dp) ? dw + 1 : n;
@@ -310,7 +429,8 @@ __global__ __launch_bounds__(256) void k_discharge(GraphView g, StateView st, Ro
                     }
                     if (gl == 0) scans += (end - base) < G ? (end - base) : G;
                     bool lose;
-                    if (chunk_pass<G>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, pushes, p.sink, to_sink) > 0)
+                    if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, pushes,
+                                             p.sink, to_sink) > 0)
                         st.res[a] = r;
                     if (el == 0) break;
                     if (r > 0 && dw >= dp && dw + 1 < cand) cand = dw + 1;
@@ -330,32 +450,51 @@ __global__ __launch_bounds__(256) void k_discharge(GraphView g, StateView st, Ro
         if (gl == 0) {
             st.dn[v] = dp;
             st.e[v] = el;
+            if (DENSE) st.touched[v] = 1;
         }
-        const int idx = wave_append(gl == 0, v, st.C, &st.ctl->nc);
-        if (gl == 0) st.owner[v] = idx;
+        if (!DENSE) {
+            const int idx = wave_append(gl == 0, v, st.C, &st.ctl->nc);
+            if (gl == 0) st.owner[v] = idx;
+        }
     }
     block_add64(to_sink, &st.e[p.sink]);
     block_add64(work, &st.ctl->work);
     block_add64(pushes, &st.ctl->pushes);
     block_add64(relabels, &st.ctl->relabels);
     block_add64(scans, &st.ctl->scans);
+    block_add64(dverts, &st.ctl->dverts);
+    block_add64(dslots, &st.ctl->dslots);
 }
 
 // ---------------------------------------------------------------------------
 // Merge (Listing 1, the two loops after the discharge): e(w) += pushes
 // received, d(w) := d'(w), new working set = touched vertices with e > 0 and
-// d < n other than the terminals.
+// d < n other than the terminals.  Each touched vertex is merged once: in
+// list mode by the candidate entry that owns it, in dense mode by the walk
+// over all vertices.
 
-template <int G>
+template <int G, bool DENSE>
 __global__ __launch_bounds__(256) void k_merge(GraphView g, StateView st, int sink, int other)
 {
-    const int nc = st.ctl->nc;
+    const int limit = DENSE ? g.n : st.ctl->nc;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups) {
-        const int w = st.C[i];
-        if (st.owner[w] != i) continue;
+    int cnt = 0;
+    int64_t mverts = 0, mslots = 0;
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < limit; i += gridDim.x * groups) {
+        int w;
+        if (DENSE) {
+            w = i;
+            if (!st.touched[w]) continue;
+        } else {
+            w = st.C[i];
+            if (st.owner[w] != i) continue;
+        }
         const int beg = g.off[w], end = g.off[w + 1];
+        if (gl == 0) {
+            mverts++;
+            mslots += end - beg;
+        }
         int64_t sum = 0;
         for (int a = beg + gl; a < end; a += G) {
             const int dl = st.delta[a];
@@ -366,17 +505,24 @@ __global__ __launch_bounds__(256) void k_merge(GraphView g, StateView st, int si
             }
         }
         sum = group_sum<G>(sum);
-        bool p = false;
+        bool pa = false;
         if (gl == 0) {
             const int64_t e = st.e[w] + sum;
             st.e[w] = e;
             const int dnew = st.dn[w];
             st.d[w] = dnew;
-            p = w != sink && w != other && e > 0 && dnew < g.n;
-            st.act[w] = p;
+            pa = w != sink && w != other && e > 0 && dnew < g.n;
+            st.act[w] = pa;
+            if (DENSE) {
+                st.touched[w] = 0;
+                cnt += pa;
+            }
         }
-        wave_append(p, w, st.A2, &st.ctl->na2);
+        if (!DENSE) wave_append(pa, w, st.A2, &st.ctl->na2);
     }
+    if (DENSE) block_add32(cnt, &st.ctl->na2);
+    block_add64(mverts, &st.ctl->mverts);
+    block_add64(mslots, &st.ctl->mslots);
 }
 
 __global__ void k_round_reset(Ctl *ctl)
@@ -423,23 +569,6 @@ __global__ void k_read_value(const int64_t *e, int t, Ctl *ctl) { ctl->value = e
 // ---------------------------------------------------------------------------
 // Launch helpers used by the host driver.
 
-template <int G>
-static void launch_discharge_t(GraphView g, StateView st, RoundParams p, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_discharge<G>, dim3(grid), dim3(256), 0, s, g, st, p);
-}
-template <int G>
-static void launch_merge_t(GraphView g, StateView st, int sink, int other, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_merge<G>, dim3(grid), dim3(256), 0, s, g, st, sink, other);
-}
-template <int G>
-static void launch_gr_level_t(GraphView g, StateView st, int level, int sink, int other,
-                              const int32_t *qin, int32_t *qout, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_gr_level<G>, dim3(grid), dim3(256), 0, s, g, st, level, sink, other, qin, qout);
-}
-
 #define MF_DISPATCH_G(G, CALL)                    \
     switch (G) {                                  \
     case 1: CALL(1); break;                       \
@@ -451,29 +580,52 @@ static void launch_gr_level_t(GraphView g, StateView st, int level, int sink, in
     default: CALL(64); break;                     \
     }
 
-void launch_discharge(int G, GraphView g, StateView st, int64_t beta, int sink, int grid, hipStream_t s)
+void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid,
+                      hipStream_t s)
 {
     RoundParams p{beta, sink};
-#define C_(X) launch_discharge_t<X>(g, st, p, grid, s)
+#define C_(X)                                                                                     \
+    if (dense) hipLaunchKernelGGL((k_discharge<X, true>), dim3(grid), dim3(256), 0, s, g, st, p); \
+    else hipLaunchKernelGGL((k_discharge<X, false>), dim3(grid), dim3(256), 0, s, g, st, p)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }
 
-void launch_merge(int G, GraphView g, StateView st, int sink, int other, int grid, hipStream_t s)
+void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int grid,
+                  hipStream_t s)
 {
-#define C_(X) launch_merge_t<X>(g, st, sink, other, grid, s)
+#define C_(X)                                                                                          \
+    if (dense) hipLaunchKernelGGL((k_merge<X, true>), dim3(grid), dim3(256), 0, s, g, st, sink, other); \
+    else hipLaunchKernelGGL((k_merge<X, false>), dim3(grid), dim3(256), 0, s, g, st, sink, other)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }
 
-void launch_gr_level(int G, GraphView g, StateView st, int level, int sink, int other,
-                     const int32_t *qin, int32_t *qout, int grid, hipStream_t s)
+void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
+                  int32_t *qout, int hubdeg, int grid, hipStream_t s)
 {
-#define C_(X) launch_gr_level_t<X>(g, st, level, sink, other, qin, qout, grid, s)
+#define C_(X) hipLaunchKernelGGL((k_gr_td<X>), dim3(grid), dim3(256), 0, s, g, st, level, sink, other, qin, qout, hubdeg)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }
 
+void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int grid,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gr_hub, dim3(grid), dim3(256), 0, s, g, st, level, sink, other, qout);
+}
+void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gr_bu, dim3(grid), dim3(256), 0, s, g, st, level, sink, other);
+}
+void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gr_collect, dim3(grid), dim3(256), 0, s, g, st, level, qout);
+}
+void launch_compact_act(GraphView g, StateView st, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact_act, dim3(grid), dim3(256), 0, s, g, st);
+}
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s)
 {

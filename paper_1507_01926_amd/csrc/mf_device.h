@@ -19,13 +19,16 @@ struct GraphView {
 // Counters written by the kernels and read back by the host driver.
 struct Ctl {
     int32_t na;            // entries of the current working-set list
-    int32_t na2;           // entries appended to the next working-set list
+    int32_t na2;           // size of the next working set (list entries or dense count)
     int32_t nc;            // entries of the candidate list
     int32_t nq[3];         // BFS frontier sizes, ring indexed by level % 3
+    int32_t nh[3];         // BFS hub-list sizes, ring indexed by level % 3
     int32_t err;           // validation error bits
-    int32_t pad;
     int64_t work;          // relabel work of the round (sum of outdeg + beta)
     int64_t pushes, relabels, scans;
+    int64_t dverts, dslots;    // vertices discharged and their slots (first pass)
+    int64_t mverts, mslots;    // vertices merged and their slots
+    int64_t gslots;            // slots examined by global-relabel levels
     int64_t cut;           // cut capacity accumulator
     int64_t value;         // scratch for the host
 };
@@ -37,10 +40,13 @@ struct Ctl {
 //   d[v]      label at the start of the round; dn[v] label after v's discharge
 //   e[v]      excess; act[v] 1 iff v is in the working set
 //   owner[w]  index of the candidate-list entry that merges w this round
+//   touched[w] 1 iff w was pushed to or discharged in the current round (dense
+//             rounds only; all zero between rounds)
 struct StateView {
     int32_t *res, *delta, *d, *dn, *owner;
     int64_t *e;
-    uint8_t *act;
+    uint8_t *act, *touched;
+    int32_t *H;            // BFS hub list (frontier vertices of high degree)
     int32_t *A, *A2;       // working-set lists (current, next)
     int32_t *C;            // candidate list (vertices touched in the round)
     int32_t *Q, *Q2;       // BFS frontiers
@@ -121,6 +127,22 @@ __device__ __forceinline__ int wave_append(bool pred, int32_t val, int32_t *list
         list[idx] = val;
     }
     return idx;
+}
+
+// Block-wide sum of a per-thread int32 into *dst with one atomic per block.
+__device__ __forceinline__ void block_add32(int32_t x, int32_t *dst)
+{
+    __shared__ int32_t part32[16];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    int w = threadIdx.x >> 6;
+    if (lane_id() == 0) part32[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t s = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) s += part32[i];
+        if (s) atomicAdd(dst, s);
+    }
+    __syncthreads();
 }
 
 // Block-wide sum of a per-thread int64 into *dst with one atomic per block.

@@ -27,10 +27,17 @@
 #include "mf_device.h"
 
 namespace mf {
-void launch_discharge(int G, GraphView g, StateView st, int64_t beta, int sink, int grid, hipStream_t s);
-void launch_merge(int G, GraphView g, StateView st, int sink, int other, int grid, hipStream_t s);
-void launch_gr_level(int G, GraphView g, StateView st, int level, int sink, int other,
-                     const int32_t *qin, int32_t *qout, int grid, hipStream_t s);
+void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid,
+                      hipStream_t s);
+void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int grid,
+                  hipStream_t s);
+void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
+                  int32_t *qout, int hubdeg, int grid, hipStream_t s);
+void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int grid,
+                   hipStream_t s);
+void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s);
+void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s);
+void launch_compact_act(GraphView g, StateView st, int grid, hipStream_t s);
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s);
 void launch_validate(GraphView g, Ctl *ctl, int grid, hipStream_t s);
@@ -74,8 +81,8 @@ struct Workspace {
     int64_t n_cap = 0, s_cap = 0;
     int32_t *res = nullptr, *delta = nullptr, *d = nullptr, *dn = nullptr, *owner = nullptr;
     int64_t *e = nullptr;
-    uint8_t *act = nullptr, *side = nullptr;
-    int32_t *A = nullptr, *A2 = nullptr, *C = nullptr, *Q = nullptr, *Q2 = nullptr;
+    uint8_t *act = nullptr, *side = nullptr, *touched = nullptr;
+    int32_t *A = nullptr, *A2 = nullptr, *C = nullptr, *Q = nullptr, *Q2 = nullptr, *H = nullptr;
     size_t bytes = 0;
 };
 
@@ -87,6 +94,7 @@ struct mf_context {
     Ctl *ctl = nullptr;        // device
     Ctl *ctl_host = nullptr;   // pinned host mirror
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t pev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // profiling
     Workspace ws;
     int num_cus = 256;
     std::string err;
@@ -220,6 +228,8 @@ mf_status mf_context_create(int device, size_t hbm_budget_bytes, mf_context **ou
         }
         for (auto &ev : ctx->ev)
             if (hipEventCreate(&ev) != hipSuccess) { st = fail(nullptr, MF_EDEVICE, "hipEventCreate failed"); break; }
+        for (auto &ev : ctx->pev)
+            if (hipEventCreate(&ev) != hipSuccess) { st = fail(nullptr, MF_EDEVICE, "hipEventCreate failed"); break; }
     } while (0);
     if (st != MF_OK) {
         mf_context_destroy(ctx);
@@ -235,12 +245,15 @@ void mf_context_destroy(mf_context *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     Workspace &w = ctx->ws;
-    void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.A, w.A2, w.C, w.Q, w.Q2};
+    void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.touched,
+                    w.A, w.A2, w.C, w.Q, w.Q2, w.H};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
     if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
     for (auto ev : ctx->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto ev : ctx->pev)
         if (ev) (void)hipEventDestroy(ev);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -382,7 +395,8 @@ static mf_status ensure_workspace(mf_context *ctx, int64_t n, int64_t slots)
     Workspace &w = ctx->ws;
     if (w.n_cap >= n && w.s_cap >= slots && w.res) return MF_OK;
     // release the old one
-    void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.A, w.A2, w.C, w.Q, w.Q2};
+    void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.touched,
+                    w.A, w.A2, w.C, w.Q, w.Q2, w.H};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     ctx->used -= std::min(ctx->used, w.bytes);
@@ -403,6 +417,8 @@ static mf_status ensure_workspace(mf_context *ctx, int64_t n, int64_t slots)
     if ((st = dalloc(ctx, (void **)&w.A2, 4 * N)) != MF_OK) return st;
     if ((st = dalloc(ctx, (void **)&w.Q, 4 * N)) != MF_OK) return st;
     if ((st = dalloc(ctx, (void **)&w.Q2, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.H, 4 * N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.touched, N)) != MF_OK) return st;
     w.n_cap = N;
     w.s_cap = S;
     w.bytes = ctx->used - before;
@@ -438,32 +454,84 @@ struct Solve {
     int G, Gm;
     int maxgrid;
     int64_t avg_deg_ceil;
+    int64_t dense_threshold;   // working sets larger than this run in dense mode
+    int64_t bu_factor;         // bottom-up BFS level when frontier * bu_factor > unvisited
+    int hubdeg;                // frontier vertices above this degree are expanded by the grid
+    bool profile;
+    // profiling accumulators
+    double ms_dis = 0, ms_mer = 0, ms_gr = 0;
+    int64_t n_dis = 0, n_mer = 0, n_gr = 0;
+    int64_t dense_rounds = 0, bu_levels = 0, td_levels = 0, grs = 0;
 };
 
-static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, int &na)
+static float elapsed(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+}
+
+// Working-set representation for the next round: a list for small sets, the
+// activity flags for large ones.  `count` is the size of the new set; when a
+// list is needed and the last step left only flags, they are compacted.
+static void prepare_working_set(Solve &S, int count, bool have_list, bool &dense)
+{
+    dense = (int64_t)count > S.dense_threshold;
+    if (!dense && !have_list) {
+        (void)hipMemsetAsync(&S.ctx->ctl->na, 0, sizeof(int32_t), S.ctx->stream);
+        launch_compact_act(S.g, S.st, grid_for(S.g.n, 256, S.maxgrid), S.ctx->stream);
+    }
+}
+
+static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, int &na, bool &dense)
 {
     mf_context *ctx = S.ctx;
     const int n = S.g.n;
     launch_gr_init(S.g, S.st, sink, grid_for(n, 256, S.maxgrid), ctx->stream);
-    int nq = 1;
+    int64_t nq = 1;
+    int64_t unvisited = n - 2;
     int level = 0;
+    bool have_list = true;
     int32_t *qin = S.st.Q, *qout = S.st.Q2;
     while (nq > 0) {
-        const int groups = 256 / S.G;
-        launch_gr_level(S.G, S.g, S.st, level, sink, other, qin, qout, grid_for(nq, groups, S.maxgrid),
-                        ctx->stream);
+        const bool bottom_up = nq * S.bu_factor > unvisited;
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
+        if (bottom_up) {
+            S.bu_levels++;
+            launch_gr_bu(S.g, S.st, level, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream);
+            have_list = false;
+        } else {
+            S.td_levels++;
+            if (!have_list) {
+                HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
+                launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
+            }
+            const int groups = 256 / S.G;
+            launch_gr_td(S.G, S.g, S.st, level, sink, other, qin, qout, S.hubdeg,
+                         grid_for(nq, groups, S.maxgrid), ctx->stream);
+            launch_gr_hub(S.g, S.st, level, sink, other, qout, ctx->num_cus * 2, ctx->stream);
+            std::swap(qin, qout);
+            have_list = true;
+        }
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[5], ctx->stream));
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
+        if (S.profile) {
+            S.ms_gr += elapsed(ctx->pev[4], ctx->pev[5]);
+            S.n_gr++;
+        }
         nq = ctx->ctl_host->nq[(level + 1) % 3];
-        std::swap(qin, qout);
+        unvisited -= nq;
         level++;
     }
     ps.levels += level - 1;
     ps.grs++;
+    S.grs++;
     launch_gr_rebuild(S.g, S.st, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream);
     mf_status st = read_ctl(ctx);
     if (st != MF_OK) return st;
-    na = ctx->ctl_host->na;
+    na = ctx->ctl_host->na2;
+    prepare_working_set(S, na, false, dense);
     return MF_OK;
 }
 
@@ -477,10 +545,11 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
     bool force = true;
     int64_t W = 0;
     int na = 0;
+    bool dense = false;
     while (true) {
         bool just = false;
         if (force || o.gr_freq_num * W > o.gr_freq_den * (o.gr_alpha * n + m)) {
-            mf_status st = global_relabel(S, sink, other, ps, na);
+            mf_status st = global_relabel(S, sink, other, ps, na, dense);
             if (st != MF_OK) return st;
             W = 0;
             force = false;
@@ -494,15 +563,36 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
         if (max_rounds > 0 && ps.rounds >= max_rounds) return MF_ETIMEOUT;
         launch_round_reset(ctx->ctl, ctx->stream);
         const int groups = 256 / S.G;
-        launch_discharge(S.G, S.g, S.st, o.gr_beta, sink, grid_for(na, groups, S.maxgrid), ctx->stream);
-        const int64_t cand_bound = (int64_t)na * (1 + S.avg_deg_ceil);
-        launch_merge(S.Gm, S.g, S.st, sink, other, grid_for(cand_bound, 256 / S.Gm, S.maxgrid), ctx->stream);
-        launch_round_end(ctx->ctl, ctx->stream);
+        const int64_t dgrid_items = dense ? n : na;
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[0], ctx->stream));
+        launch_discharge(S.G, dense, S.g, S.st, o.gr_beta, sink, grid_for(dgrid_items, groups, S.maxgrid),
+                         ctx->stream);
+        if (S.profile) {
+            HIPCHK(ctx, hipEventRecord(ctx->pev[1], ctx->stream));
+            HIPCHK(ctx, hipEventRecord(ctx->pev[2], ctx->stream));
+        }
+        const int64_t cand_items = dense ? n : (int64_t)na * (1 + S.avg_deg_ceil);
+        launch_merge(S.Gm, dense, S.g, S.st, sink, other, grid_for(cand_items, 256 / S.Gm, S.maxgrid),
+                     ctx->stream);
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[3], ctx->stream));
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
+        if (S.profile) {
+            S.ms_dis += elapsed(ctx->pev[0], ctx->pev[1]);
+            S.ms_mer += elapsed(ctx->pev[2], ctx->pev[3]);
+            S.n_dis++;
+            S.n_mer++;
+        }
+        if (dense) S.dense_rounds++;
         W += ctx->ctl_host->work + o.gr_round_charge;
-        na = ctx->ctl_host->na;
-        std::swap(S.st.A, S.st.A2);
+        const int count = ctx->ctl_host->na2;
+        const bool was_dense = dense;
+        prepare_working_set(S, count, !was_dense, dense);
+        if (!was_dense && !dense) {
+            launch_round_end(ctx->ctl, ctx->stream);   // na = na2
+            std::swap(S.st.A, S.st.A2);
+        }
+        na = count;
         ps.rounds++;
     }
 }
@@ -547,6 +637,8 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.st.owner = w.owner;
     S.st.e = w.e;
     S.st.act = w.act;
+    S.st.touched = w.touched;
+    S.st.H = w.H;
     S.st.A = w.A;
     S.st.A2 = w.A2;
     S.st.C = w.C;
@@ -558,13 +650,17 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.Gm = o.lanes_per_merge > 0 ? pick_lanes(o.lanes_per_merge, 1, 1) : S.G;
     S.maxgrid = ctx->num_cus * 16;
     S.avg_deg_ceil = (dg->slots + dg->n - 1) / std::max<int64_t>(1, dg->n);
+    S.dense_threshold = std::max<int64_t>(4096, dg->n / 64);
+    S.bu_factor = 8;
+    S.hubdeg = 64 * S.G;
+    S.profile = (o.flags & MF_PROFILE) != 0;
 
     const int n = dg->n;
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
     launch_init_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
     launch_saturate(S.g, S.st, ctx->num_cus * 4, ctx->stream);
-    launch_merge(S.Gm, S.g, S.st, dg->t, dg->s, ctx->num_cus * 4, ctx->stream);
+    launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, grid_for(n, 256 / S.Gm, S.maxgrid), ctx->stream);
 
     PhaseStats p1;
     mf_status ph = run_phase(S, dg->t, dg->s, o.max_rounds, p1);
@@ -592,7 +688,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     }
     if (flow_dev) launch_flow(S.g, w.res, flow_dev, grid_for(dg->slots, 256, S.maxgrid), ctx->stream);
     HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if ((st = read_ctl(ctx)) != MF_OK) return st;
     HIPCHK(ctx, hipGetLastError());
 
     if (value) *value = val;
@@ -613,6 +709,31 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
         (void)hipEventElapsedTime(&ms2, ctx->ev[0], ctx->ev[2]);
         stats->ms_preflow = ms1;
         stats->ms_total = ms2;
+        if (S.profile) {
+            // Algorithmic bytes (the per-unit model of the design notes):
+            //  discharge: 40 B per discharged vertex (list entry or flag, two
+            //    offsets, label, excess, new label and excess, touched mark),
+            //    13 B per slot of a discharged vertex (residual, head, head's
+            //    label and activity flag), 16 B per push (reverse slot index,
+            //    residual, delta, touched mark or candidate entry), plus the
+            //    activity flags of all n vertices in a dense round;
+            //  merge: 41 B per merged vertex, 4 B per slot of it (delta), 12 B
+            //    per push received (residual update, delta clear), plus n B in
+            //    a dense round;
+            //  global relabel: 12 B per slot examined (head, reverse index,
+            //    residual, label), 9 B per vertex per relabel (labels reset,
+            //    working-set rebuild) and 4 B per vertex per bottom-up level.
+            const Ctl &c = *ctx->ctl_host;
+            stats->ms_discharge = S.ms_dis;
+            stats->ms_merge = S.ms_mer;
+            stats->ms_global_relabel = S.ms_gr;
+            stats->discharge_launches = S.n_dis;
+            stats->merge_launches = S.n_mer;
+            stats->global_relabel_launches = S.n_gr;
+            stats->discharge_bytes = 40 * c.dverts + 13 * c.dslots + 16 * c.pushes + S.dense_rounds * (int64_t)n;
+            stats->merge_bytes = 41 * c.mverts + 4 * c.mslots + 12 * c.pushes + S.dense_rounds * (int64_t)n;
+            stats->global_relabel_bytes = 12 * c.gslots + S.grs * 9 * (int64_t)n + S.bu_levels * 4 * (int64_t)n;
+        }
     }
     return timed_out ? fail(ctx, MF_ETIMEOUT, "round limit %lld reached", (long long)o.max_rounds) : MF_OK;
 }
