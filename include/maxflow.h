@@ -77,8 +77,13 @@ typedef struct {
 
 /* flags */
 #define MF_PREFLOW_ONLY 0x1u   /* stop at the maximum preflow (Sec. 2.1); flow output not produced */
-#define MF_PROFILE      0x2u   /* time the discharge, merge and global-relabel kernels with HIP
-                                  events on the context's stream and count their algorithmic bytes */
+#define MF_PROFILE      0x2u   /* time the solver kernels with HIP events on the context's stream
+                                  and count their algorithmic bytes */
+#define MF_PERSISTENT   0x4u   /* run each phase as one persistent cooperative kernel with grid
+                                  barriers instead of one launch per round and breadth-first level
+                                  (the default); both give identical results.  On MI355X the
+                                  launches are faster for one large instance: each grid barrier
+                                  costs a cache write-back and invalidation per block */
 
 typedef struct {
     /* Global-relabel schedule (Sec. 3 and its footnote): a global relabel
@@ -91,7 +96,9 @@ typedef struct {
     uint32_t flags;
     int32_t lanes_per_vertex;    /* lanes that discharge one vertex: 0 = automatic, else 1..64, power of 2 */
     int32_t lanes_per_merge;     /* lanes that merge one vertex's excess: 0 = automatic */
-    int32_t reserved[5];
+    int32_t dense_threshold;     /* working sets above this size run in dense mode: 0 = automatic */
+    int32_t blocks_per_cu;       /* persistent kernel blocks per compute unit: 0 = occupancy limit */
+    int32_t reserved[3];
 } mf_options;
 
 typedef struct {
@@ -107,6 +114,10 @@ typedef struct {
     double ms_discharge, ms_merge, ms_global_relabel;
     int64_t discharge_launches, merge_launches, global_relabel_launches;
     int64_t discharge_bytes, merge_bytes, global_relabel_bytes;
+    /* persistent mode: summed duration and count of the phase kernel launches
+     * (with MF_PROFILE the per-step times above stay 0 in this mode) */
+    double ms_phase_kernel;
+    int64_t phase_launches;
 } mf_stats;
 
 typedef struct mf_context mf_context;

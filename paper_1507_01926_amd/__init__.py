@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "MF_OK", 1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: 
                 5: "MF_EAGAIN", 6: "MF_ECANCELED", 7: "MF_ENOTFOUND"}
 MF_PREFLOW_ONLY = 0x1
 MF_PROFILE = 0x2
+MF_PERSISTENT = 0x4
 
 
 class MaxflowError(RuntimeError):
@@ -41,7 +42,8 @@ class mf_options(ctypes.Structure):
                 ("gr_alpha", ctypes.c_int64), ("gr_beta", ctypes.c_int64),
                 ("gr_round_charge", ctypes.c_int64), ("max_rounds", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("lanes_per_vertex", ctypes.c_int32),
-                ("lanes_per_merge", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("lanes_per_merge", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class mf_stats(ctypes.Structure):
@@ -52,7 +54,8 @@ class mf_stats(ctypes.Structure):
         ("ms_discharge", ctypes.c_double), ("ms_merge", ctypes.c_double),
         ("ms_global_relabel", ctypes.c_double)] + [(k, ctypes.c_int64) for k in (
         "discharge_launches", "merge_launches", "global_relabel_launches", "discharge_bytes",
-        "merge_bytes", "global_relabel_bytes")]
+        "merge_bytes", "global_relabel_bytes")] + [
+        ("ms_phase_kernel", ctypes.c_double), ("phase_launches", ctypes.c_int64)]
 
 
 _LIB = None
@@ -110,6 +113,8 @@ def options(**kw) -> mf_options:
             o.flags = (o.flags | MF_PREFLOW_ONLY) if v else (o.flags & ~MF_PREFLOW_ONLY)
         elif k == "profile":
             o.flags = (o.flags | MF_PROFILE) if v else (o.flags & ~MF_PROFILE)
+        elif k == "persistent":
+            o.flags = (o.flags | MF_PERSISTENT) if v else (o.flags & ~MF_PERSISTENT)
         else:
             setattr(o, k, int(v))
     return o

@@ -18,6 +18,7 @@
 // A global relabel (Sec. 2.1, Sec. 3) is a level-synchronous reverse BFS from
 // the sink (k_gr_init, k_gr_level per level, k_gr_rebuild).
 #include "mf_device.h"
+#include "mf_steps.h"
 
 namespace mf {
 
@@ -176,6 +177,8 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
     const int groups = blockDim.x / G;
     const int next = level + 1;
     int64_t gslots = 0;
+    MF_STAGE(stage);
+    stage_init(stage);
     for (int i = blockIdx.x * groups + threadIdx.x / G; i < nq; i += gridDim.x * groups) {
         const int v = qin[i];
         const int beg = g.off[v], end = g.off[v + 1];
@@ -197,9 +200,10 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
                     }
                 }
             }
-            wave_append(claim, w, qout, &st.ctl->nq[next % 3]);
+            stage_append(stage, claim, w, qout, &st.ctl->nq[next % 3]);
         }
     }
+    stage_flush(stage, qout, &st.ctl->nq[next % 3]);
     block_add64(gslots, &st.ctl->gslots);
 }
 
@@ -210,6 +214,8 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
     const int nh = st.ctl->nh[level % 3];
     const int next = level + 1;
     int64_t gslots = 0;
+    MF_STAGE(stage);
+    stage_init(stage);
     for (int h = 0; h < nh; h++) {
         const int v = st.H[h];
         const int beg = g.off[v], end = g.off[v + 1];
@@ -227,9 +233,10 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
                     }
                 }
             }
-            wave_append(claim, w, qout, &st.ctl->nq[next % 3]);
+            stage_append(stage, claim, w, qout, &st.ctl->nq[next % 3]);
         }
     }
+    stage_flush(stage, qout, &st.ctl->nq[next % 3]);
     block_add64(gslots, &st.ctl->gslots);
 }
 
@@ -260,13 +267,17 @@ __global__ __launch_bounds__(256) void k_gr_bu(GraphView g, StateView st, int le
 }
 
 // Frontier list of a level from the labels (after a bottom-up level).
-__global__ void k_gr_collect(GraphView g, StateView st, int level, int32_t *__restrict__ qout)
+__global__ __launch_bounds__(256) void k_gr_collect(GraphView g, StateView st, int level,
+                                                    int32_t *__restrict__ qout)
 {
+    MF_STAGE(stage);
+    stage_init(stage);
     for (int base = blockIdx.x * blockDim.x; base < g.n; base += gridDim.x * blockDim.x) {
         const int v = base + threadIdx.x;
         const bool p = v < g.n && st.d[v] == level;
-        wave_append(p, v, qout, &st.ctl->nq[(level + 2) % 3]);
+        stage_append(stage, p, v, qout, &st.ctl->nq[(level + 2) % 3]);
     }
+    stage_flush(stage, qout, &st.ctl->nq[(level + 2) % 3]);
 }
 
 // Working set after a global relabel: every vertex other than the two
@@ -283,13 +294,16 @@ __global__ void k_gr_rebuild(GraphView g, StateView st, int sink, int other)
 }
 
 // Working-set list from the activity flags.
-__global__ void k_compact_act(GraphView g, StateView st)
+__global__ __launch_bounds__(256) void k_compact_act(GraphView g, StateView st)
 {
+    MF_STAGE(stage);
+    stage_init(stage);
     for (int base = blockIdx.x * blockDim.x; base < g.n; base += gridDim.x * blockDim.x) {
         const int v = base + threadIdx.x;
         const bool p = v < g.n && st.act[v];
-        wave_append(p, v, st.A, &st.ctl->na);
+        stage_append(stage, p, v, st.A, &st.ctl->na);
     }
+    stage_flush(stage, st.A, &st.ctl->na);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,169 +315,41 @@ __global__ void k_compact_act(GraphView g, StateView st)
 // the kernels walk all vertices: the working set is act[], and touched[]
 // marks the vertices to merge, which avoids list appends altogether.
 
-struct RoundParams {
-    int64_t beta;      // work per relabel = outdeg + beta
-    int sink;          // pushes into the sink go straight to its reverse slot and excess
-};
-
-// One pass over a chunk of up to G slots, in slot order.  Each lane holds one
-// slot: r its residual, w its head, dw = d(w), aw = act(w).  Pushes along
-// admissible arcs the vertex may use take min(r, e - excl) where excl is the
-// total residual of the admissible, usable arcs before it in slot order: the
-// result of visiting the arcs one after another.
-//
-// The sink never discharges and nobody reads its own slots or its excess
-// during a round, so a push into the sink updates the reverse slot directly
-// (each slot has one pusher) and is added to the sink's excess once per block.
-template <int G, bool DENSE>
-__device__ __forceinline__ int chunk_pass(const GraphView &g, StateView &st, int v, int dv, int dp,
-                                          int gl, int a, int &r, int w, int dw, bool aw,
-                                          int64_t &el, bool &lose, int64_t &pushes, int sink,
-                                          int64_t &to_sink)
+// List mode: the working set is A[0 .. na).
+template <int G>
+__global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView st, RoundParams p)
 {
-    const bool adm = r > 0 && dp == dw + 1;
-    const bool win = (dv == dw + 1) || (dv < dw - 1) || (dv == dw && v < w);
-    lose = adm && aw && !win;
-    const bool use = adm && !lose;
-    const int64_t amt = use ? (int64_t)r : 0;
-    const int64_t incl = group_incl_scan<G>(amt, gl);
-    const int64_t tot = group_bcast<G>(incl, G - 1);
-    const int64_t excl = incl - amt;
-    int dl = 0;
-    if (use && excl < el) {
-        const int64_t rem = el - excl;
-        dl = rem < (int64_t)r ? (int)rem : r;
-    }
-    const bool into_sink = w == sink;
-    if (dl > 0) {
-        r -= dl;
-        pushes++;
-        if (into_sink) {
-            st.res[g.rev[a]] += dl;
-            to_sink += dl;
-        } else {
-            st.delta[g.rev[a]] = dl;
-            if (DENSE) st.touched[w] = 1;
-        }
-    }
-    if (!DENSE) {
-        const bool app = dl > 0 && !into_sink;
-        const int idx = wave_append(app, w, st.C, &st.ctl->nc);
-        if (app) st.owner[w] = idx;
-    }
-    el = tot >= el ? 0 : el - tot;
-    return dl;
-}
-
-template <int G, bool DENSE>
-__global__ __launch_bounds__(256) void k_discharge(GraphView g, StateView st, RoundParams p)
-{
-    const int limit = DENSE ? g.n : st.ctl->na;
+    const int na = st.ctl->na;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
-    const int n = g.n;
-    int64_t work = 0, pushes = 0, relabels = 0, scans = 0, to_sink = 0, dverts = 0, dslots = 0;
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < limit; i += gridDim.x * groups) {
-        int v;
-        if (DENSE) {
-            v = i;
-            if (!st.act[v]) continue;
-        } else {
-            v = st.A[i];
-        }
-        const int beg = g.off[v], end = g.off[v + 1], deg = end - beg;
-        if (gl == 0) {
-            dverts++;
-            dslots += deg;
-        }
-        const int dv = st.d[v];
-        int dp = dv;
-        int64_t el = st.e[v];
-        if (deg <= G) {
-            // The vertex's slots stay in registers across passes.
-            const int a = beg + gl;
-            int r = 0, w = -1, dw = 0;
-            bool aw = false;
-            if (gl < deg) {
-                r = st.res[a];
-                if (r > 0) {
-                    w = g.head[a];
-                    dw = st.d[w];
-                    aw = st.act[w] != 0;
-                }
-            }
-            bool dirty = false;
-            while (el > 0) {
-                if (gl == 0) scans += deg;
-                bool lose;
-                if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, pushes, p.sink,
-                                         to_sink) > 0)
-                    dirty = true;
-                if (el == 0) break;
-                const int cand = (r > 0 && dw >= dp) ? dw + 1 : n;
-                const int nl = group_min<G>(cand);
-                if (group_or<G>(lose ? 1 : 0)) break;          // skipped
-                dp = nl < n ? nl : n;                            // relabel
-                if (gl == 0) {
-                    work += deg + p.beta;
-                    relabels++;
-                }
-                if (dp >= n) break;
-            }
-            if (dirty) st.res[a] = r;
-        } else {
-            while (el > 0) {
-                int cand = n;
-                int sk = 0;
-                for (int base = beg; base < end; base += G) {
-                    const int a = base + gl;
-                    int r = 0, w = -1, dw = 0;
-                    bool aw = false;
-                    if (a < end) {
-                        r = st.res[a];
-                        if (r > 0) {
-                            w = g.head[a];
-                            dw = st.d[w];
-                            aw = st.act[w] != 0;
-                        }
-                    }
-                    if (gl == 0) scans += (end - base) < G ? (end - base) : G;
-                    bool lose;
-                    if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, pushes,
-                                             p.sink, to_sink) > 0)
-                        st.res[a] = r;
-                    if (el == 0) break;
-                    if (r > 0 && dw >= dp && dw + 1 < cand) cand = dw + 1;
-                    sk |= lose ? 1 : 0;
-                }
-                if (el == 0) break;
-                const int nl = group_min<G>(cand);
-                if (group_or<G>(sk)) break;
-                dp = nl < n ? nl : n;
-                if (gl == 0) {
-                    work += deg + p.beta;
-                    relabels++;
-                }
-                if (dp >= n) break;
-            }
-        }
-        if (gl == 0) {
-            st.dn[v] = dp;
-            st.e[v] = el;
-            if (DENSE) st.touched[v] = 1;
-        }
-        if (!DENSE) {
-            const int idx = wave_append(gl == 0, v, st.C, &st.ctl->nc);
-            if (gl == 0) st.owner[v] = idx;
+    DisAcc acc;
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups)
+        discharge_vertex<G, false>(g, st, p, st.A[i], gl, acc);
+    discharge_flush(st, p, acc);
+}
+
+// Dense mode: every wave reads 64 activity flags, and its 64/G groups take the
+// active vertices among them in turn (compaction inside the wave, no lists).
+template <int G>
+__global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView st, RoundParams p)
+{
+    constexpr int GPW = 64 / G;
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    const int grp = lane / G;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    DisAcc acc;
+    for (int base = wave * 64; base < g.n; base += nwaves * 64) {
+        const int v0 = base + lane;
+        const uint64_t mask = __ballot(v0 < g.n && st.act[v0] != 0);
+        const int cnt = __popcll(mask);
+        for (int k0 = 0; k0 < cnt; k0 += GPW) {
+            const int k = k0 + grp;
+            if (k < cnt) discharge_vertex<G, true>(g, st, p, base + nth_set_bit(mask, k), gl, acc);
         }
     }
-    block_add64(to_sink, &st.e[p.sink]);
-    block_add64(work, &st.ctl->work);
-    block_add64(pushes, &st.ctl->pushes);
-    block_add64(relabels, &st.ctl->relabels);
-    block_add64(scans, &st.ctl->scans);
-    block_add64(dverts, &st.ctl->dverts);
-    block_add64(dslots, &st.ctl->dslots);
+    discharge_flush(st, p, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -473,56 +359,41 @@ __global__ __launch_bounds__(256) void k_discharge(GraphView g, StateView st, Ro
 // list mode by the candidate entry that owns it, in dense mode by the walk
 // over all vertices.
 
-template <int G, bool DENSE>
-__global__ __launch_bounds__(256) void k_merge(GraphView g, StateView st, int sink, int other)
+template <int G>
+__global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, int sink, int other)
 {
-    const int limit = DENSE ? g.n : st.ctl->nc;
+    const int nc = st.ctl->nc;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
-    int cnt = 0;
-    int64_t mverts = 0, mslots = 0;
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < limit; i += gridDim.x * groups) {
-        int w;
-        if (DENSE) {
-            w = i;
-            if (!st.touched[w]) continue;
-        } else {
-            w = st.C[i];
-            if (st.owner[w] != i) continue;
-        }
-        const int beg = g.off[w], end = g.off[w + 1];
-        if (gl == 0) {
-            mverts++;
-            mslots += end - beg;
-        }
-        int64_t sum = 0;
-        for (int a = beg + gl; a < end; a += G) {
-            const int dl = st.delta[a];
-            if (dl != 0) {
-                st.res[a] += dl;
-                st.delta[a] = 0;
-                sum += dl;
-            }
-        }
-        sum = group_sum<G>(sum);
-        bool pa = false;
-        if (gl == 0) {
-            const int64_t e = st.e[w] + sum;
-            st.e[w] = e;
-            const int dnew = st.dn[w];
-            st.d[w] = dnew;
-            pa = w != sink && w != other && e > 0 && dnew < g.n;
-            st.act[w] = pa;
-            if (DENSE) {
-                st.touched[w] = 0;
-                cnt += pa;
-            }
-        }
-        if (!DENSE) wave_append(pa, w, st.A2, &st.ctl->na2);
+    MerAcc acc;
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups) {
+        const int w = st.C[i];
+        if (st.owner[w] != i) continue;
+        merge_vertex<G, false>(g, st, w, gl, sink, other, acc);
     }
-    if (DENSE) block_add32(cnt, &st.ctl->na2);
-    block_add64(mverts, &st.ctl->mverts);
-    block_add64(mslots, &st.ctl->mslots);
+    merge_flush(st, false, acc);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, int sink, int other)
+{
+    constexpr int GPW = 64 / G;
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    const int grp = lane / G;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    MerAcc acc;
+    for (int base = wave * 64; base < g.n; base += nwaves * 64) {
+        const int v0 = base + lane;
+        const uint64_t mask = __ballot(v0 < g.n && st.touched[v0] != 0);
+        const int cnt = __popcll(mask);
+        for (int k0 = 0; k0 < cnt; k0 += GPW) {
+            const int k = k0 + grp;
+            if (k < cnt) merge_vertex<G, true>(g, st, base + nth_set_bit(mask, k), gl, sink, other, acc);
+        }
+    }
+    merge_flush(st, true, acc);
 }
 
 __global__ void k_round_reset(Ctl *ctl)
@@ -584,9 +455,9 @@ void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta
                       hipStream_t s)
 {
     RoundParams p{beta, sink};
-#define C_(X)                                                                                     \
-    if (dense) hipLaunchKernelGGL((k_discharge<X, true>), dim3(grid), dim3(256), 0, s, g, st, p); \
-    else hipLaunchKernelGGL((k_discharge<X, false>), dim3(grid), dim3(256), 0, s, g, st, p)
+#define C_(X)                                                                                   \
+    if (dense) hipLaunchKernelGGL((k_discharge_dense<X>), dim3(grid), dim3(256), 0, s, g, st, p); \
+    else hipLaunchKernelGGL((k_discharge_list<X>), dim3(grid), dim3(256), 0, s, g, st, p)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }
@@ -594,9 +465,9 @@ void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta
 void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int grid,
                   hipStream_t s)
 {
-#define C_(X)                                                                                          \
-    if (dense) hipLaunchKernelGGL((k_merge<X, true>), dim3(grid), dim3(256), 0, s, g, st, sink, other); \
-    else hipLaunchKernelGGL((k_merge<X, false>), dim3(grid), dim3(256), 0, s, g, st, sink, other)
+#define C_(X)                                                                                        \
+    if (dense) hipLaunchKernelGGL((k_merge_dense<X>), dim3(grid), dim3(256), 0, s, g, st, sink, other); \
+    else hipLaunchKernelGGL((k_merge_list<X>), dim3(grid), dim3(256), 0, s, g, st, sink, other)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }

@@ -29,6 +29,9 @@ struct Ctl {
     int64_t dverts, dslots;    // vertices discharged and their slots (first pass)
     int64_t mverts, mslots;    // vertices merged and their slots
     int64_t gslots;            // slots examined by global-relabel levels
+    // results of a persistent phase launch
+    int64_t p_rounds, p_grs, p_levels, p_dense_rounds, p_bu_levels;
+    int32_t p_status, p_lists;
     int64_t cut;           // cut capacity accumulator
     int64_t value;         // scratch for the host
 };
@@ -128,6 +131,83 @@ __device__ __forceinline__ int wave_append(bool pred, int32_t val, int32_t *list
     }
     return idx;
 }
+
+// Position of the k-th (0-based) set bit of m; k < popcount(m).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = (m >> pos) & ((1ull << w) - 1ull);
+        const int c = __popcll(low);
+        if (k >= c) {
+            k -= c;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+// Block-staged list append.  Entries collect in an LDS buffer of the block
+// (LDS atomics only); the block writes them to the global list with one
+// global atomic when the kernel ends (stage_flush).  If the buffer is full the
+// entries go straight to the global list with one atomic per wave.
+constexpr int STAGE_CAP = 2048;
+
+struct Stage {
+    int32_t *buf;      // LDS [STAGE_CAP]
+    int32_t *cnt;      // LDS counter
+    int32_t *base;     // LDS: global position of the block's entries
+};
+
+__device__ __forceinline__ void stage_init(Stage &sg)
+{
+    if (threadIdx.x == 0) *sg.cnt = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void stage_append(Stage &sg, bool pred, int32_t val, int32_t *list,
+                                             int32_t *count)
+{
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const int c = __popcll(mask);
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int pos = 0;
+    if (lane_id() == leader) pos = atomicAdd(sg.cnt, c);   // the LDS counter only grows
+    pos = __shfl(pos, leader);
+    // positions below STAGE_CAP go to LDS, the rest straight to the global list
+    const int first_over = pos > STAGE_CAP ? pos : STAGE_CAP;
+    const int n_over = pos + c - first_over;
+    int g0 = 0;
+    if (n_over > 0) {
+        if (lane_id() == leader) g0 = atomicAdd(count, n_over);
+        g0 = __shfl(g0, leader);
+    }
+    if (pred) {
+        const int idx = pos + lanes_below(mask);
+        if (idx < STAGE_CAP)
+            sg.buf[idx] = val;
+        else
+            list[g0 + idx - first_over] = val;
+    }
+}
+
+// Must be reached by every thread of the block.
+__device__ __forceinline__ void stage_flush(Stage &sg, int32_t *list, int32_t *count)
+{
+    __syncthreads();
+    const int total = *sg.cnt < STAGE_CAP ? *sg.cnt : STAGE_CAP;
+    if (threadIdx.x == 0) *sg.base = total ? atomicAdd(count, total) : 0;
+    __syncthreads();
+    const int g0 = *sg.base;
+    for (int j = threadIdx.x; j < total; j += blockDim.x) list[g0 + j] = sg.buf[j];
+}
+
+#define MF_STAGE(name)                           \
+    __shared__ int32_t name##_buf[STAGE_CAP];    \
+    __shared__ int32_t name##_cnt, name##_base;  \
+    Stage name{name##_buf, &name##_cnt, &name##_base}
 
 // Block-wide sum of a per-thread int32 into *dst with one atomic per block.
 __device__ __forceinline__ void block_add32(int32_t x, int32_t *dst)

@@ -1,0 +1,218 @@
+// Per-vertex steps of a synchronous round, shared by the host-driven kernels
+// and the persistent solver kernel.
+#pragma once
+#include "mf_device.h"
+
+namespace mf {
+
+struct RoundParams {
+    int64_t beta;      // work per relabel = outdeg + beta
+    int sink;          // pushes into the sink go straight to its reverse slot and excess
+};
+
+// One pass over a chunk of up to G slots, in slot order.  Each lane holds one
+// slot: r its residual, w its head, dw = d(w), aw = act(w).  Pushes along
+// admissible arcs the vertex may use take min(r, e - excl) where excl is the
+// total residual of the admissible, usable arcs before it in slot order: the
+// result of visiting the arcs one after another.
+//
+// The sink never discharges and nobody reads its own slots or its excess
+// during a round, so a push into the sink updates the reverse slot directly
+// (each slot has one pusher) and is added to the sink's excess once per block.
+template <int G, bool DENSE>
+__device__ __forceinline__ int chunk_pass(const GraphView &g, StateView &st, int v, int dv, int dp,
+                                          int gl, int a, int &r, int w, int dw, bool aw,
+                                          int64_t &el, bool &lose, int64_t &pushes, int sink,
+                                          int64_t &to_sink)
+{
+    const bool adm = r > 0 && dp == dw + 1;
+    const bool win = (dv == dw + 1) || (dv < dw - 1) || (dv == dw && v < w);
+    lose = adm && aw && !win;
+    const bool use = adm && !lose;
+    const int64_t amt = use ? (int64_t)r : 0;
+    const int64_t incl = group_incl_scan<G>(amt, gl);
+    const int64_t tot = group_bcast<G>(incl, G - 1);
+    const int64_t excl = incl - amt;
+    int dl = 0;
+    if (use && excl < el) {
+        const int64_t rem = el - excl;
+        dl = rem < (int64_t)r ? (int)rem : r;
+    }
+    const bool into_sink = w == sink;
+    if (dl > 0) {
+        r -= dl;
+        pushes++;
+        if (into_sink) {
+            st.res[g.rev[a]] += dl;
+            to_sink += dl;
+        } else {
+            st.delta[g.rev[a]] = dl;
+            if (DENSE) st.touched[w] = 1;
+        }
+    }
+    if (!DENSE) {
+        const bool app = dl > 0 && !into_sink;
+        const int idx = wave_append(app, w, st.C, &st.ctl->nc);
+        if (app) st.owner[w] = idx;
+    }
+    el = tot >= el ? 0 : el - tot;
+    return dl;
+}
+
+struct DisAcc {
+    int64_t work = 0, pushes = 0, relabels = 0, scans = 0, to_sink = 0, dverts = 0, dslots = 0;
+};
+
+// Full discharge of one vertex v by a group of G lanes (the loop body of
+// Listing 1 for one element of the working set).
+template <int G, bool DENSE>
+__device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &st, const RoundParams &p,
+                                                 int v, int gl, DisAcc &acc)
+{
+    const int n = g.n;
+    const int beg = g.off[v], end = g.off[v + 1], deg = end - beg;
+    if (gl == 0) {
+        acc.dverts++;
+        acc.dslots += deg;
+    }
+    const int dv = st.d[v];
+    int dp = dv;
+    int64_t el = st.e[v];
+    if (deg <= G) {
+        // The vertex's slots stay in registers across passes.
+        const int a = beg + gl;
+        int r = 0, w = -1, dw = 0;
+        bool aw = false;
+        if (gl < deg) {
+            r = st.res[a];
+            if (r > 0) {
+                w = g.head[a];
+                dw = st.d[w];
+                aw = st.act[w] != 0;
+            }
+        }
+        bool dirty = false;
+        while (el > 0) {
+            if (gl == 0) acc.scans += deg;
+            bool lose;
+            if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, acc.pushes, p.sink,
+                                     acc.to_sink) > 0)
+                dirty = true;
+            if (el == 0) break;
+            const int cand = (r > 0 && dw >= dp) ? dw + 1 : n;
+            const int nl = group_min<G>(cand);
+            if (group_or<G>(lose ? 1 : 0)) break;          // skipped
+            dp = nl < n ? nl : n;                            // relabel
+            if (gl == 0) {
+                acc.work += deg + p.beta;
+                acc.relabels++;
+            }
+            if (dp >= n) break;
+        }
+        if (dirty) st.res[a] = r;
+    } else {
+        while (el > 0) {
+            int cand = n;
+            int sk = 0;
+            for (int base = beg; base < end; base += G) {
+                const int a = base + gl;
+                int r = 0, w = -1, dw = 0;
+                bool aw = false;
+                if (a < end) {
+                    r = st.res[a];
+                    if (r > 0) {
+                        w = g.head[a];
+                        dw = st.d[w];
+                        aw = st.act[w] != 0;
+                    }
+                }
+                if (gl == 0) acc.scans += (end - base) < G ? (end - base) : G;
+                bool lose;
+                if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, acc.pushes, p.sink,
+                                         acc.to_sink) > 0)
+                    st.res[a] = r;
+                if (el == 0) break;
+                if (r > 0 && dw >= dp && dw + 1 < cand) cand = dw + 1;
+                sk |= lose ? 1 : 0;
+            }
+            if (el == 0) break;
+            const int nl = group_min<G>(cand);
+            if (group_or<G>(sk)) break;
+            dp = nl < n ? nl : n;
+            if (gl == 0) {
+                acc.work += deg + p.beta;
+                acc.relabels++;
+            }
+            if (dp >= n) break;
+        }
+    }
+    if (gl == 0) {
+        st.dn[v] = dp;
+        st.e[v] = el;
+        if (DENSE) st.touched[v] = 1;
+    }
+    if (!DENSE) {
+        const int idx = wave_append(gl == 0, v, st.C, &st.ctl->nc);
+        if (gl == 0) st.owner[v] = idx;
+    }
+}
+
+__device__ __forceinline__ void discharge_flush(StateView &st, const RoundParams &p, DisAcc &acc)
+{
+    block_add64(acc.to_sink, &st.e[p.sink]);
+    block_add64(acc.work, &st.ctl->work);
+    block_add64(acc.pushes, &st.ctl->pushes);
+    block_add64(acc.relabels, &st.ctl->relabels);
+    block_add64(acc.scans, &st.ctl->scans);
+    block_add64(acc.dverts, &st.ctl->dverts);
+    block_add64(acc.dslots, &st.ctl->dslots);
+}
+
+struct MerAcc {
+    int cnt = 0;
+    int64_t mverts = 0, mslots = 0;
+};
+
+template <int G, bool DENSE>
+__device__ __forceinline__ void merge_vertex(const GraphView &g, StateView &st, int w, int gl, int sink,
+                                             int other, MerAcc &acc)
+{
+    const int beg = g.off[w], end = g.off[w + 1];
+    if (gl == 0) {
+        acc.mverts++;
+        acc.mslots += end - beg;
+    }
+    int64_t sum = 0;
+    for (int a = beg + gl; a < end; a += G) {
+        const int dl = st.delta[a];
+        if (dl != 0) {
+            st.res[a] += dl;
+            st.delta[a] = 0;
+            sum += dl;
+        }
+    }
+    sum = group_sum<G>(sum);
+    bool pa = false;
+    if (gl == 0) {
+        const int64_t e = st.e[w] + sum;
+        st.e[w] = e;
+        const int dnew = st.dn[w];
+        st.d[w] = dnew;
+        pa = w != sink && w != other && e > 0 && dnew < g.n;
+        st.act[w] = pa;
+        if (DENSE) {
+            st.touched[w] = 0;
+            acc.cnt += pa;
+        }
+    }
+    if (!DENSE) wave_append(pa, w, st.A2, &st.ctl->na2);
+}
+
+__device__ __forceinline__ void merge_flush(StateView &st, bool dense, MerAcc &acc)
+{
+    if (dense) block_add32(acc.cnt, &st.ctl->na2);
+    block_add64(acc.mverts, &st.ctl->mverts);
+    block_add64(acc.mslots, &st.ctl->mslots);
+}
+
+}  // namespace mf

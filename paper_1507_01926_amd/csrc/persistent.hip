@@ -1,0 +1,396 @@
+// Persistent solver kernel: one cooperative launch runs a whole phase of the
+// synchronous push-relabel method (Sec. 3.1, Listing 1): global relabels
+// (Listing 2, one breadth-first level per step) and rounds (discharge, then
+// merge), with a grid-wide barrier between steps instead of kernel launches
+// and host round trips.  Every block takes the same control decisions from
+// the same counters read after a barrier, so the blocks stay in lock step.
+//
+// The grid barrier waits a bounded time: if a block does not arrive within
+// the limit (which no correct step comes near), the barrier sets an abort
+// flag, every block leaves at its next barrier, and the host reports a
+// device error.
+#include "mf_device.h"
+#include "mf_steps.h"
+
+namespace mf {
+
+struct GridBar {
+    unsigned count;
+    unsigned gen;
+    int abort;
+    int pad;
+};
+
+struct PhaseParams {
+    int sink, other;
+    int64_t freq_num, freq_den, alpha, beta, round_charge, max_rounds;
+    int64_t dense_threshold, bu_factor;
+    int hubdeg;
+    uint64_t limit_ticks;    // barrier wait limit in wall-clock ticks
+};
+
+// Memory ordering: every wave waits for its own outstanding stores before the
+// block barrier; thread 0 then releases the block's writes to device scope
+// (one L2 write-back for the block) before it arrives, and after the other
+// blocks have arrived it acquires (one cache invalidation for the block's
+// compute unit) before the block goes on.
+__device__ __forceinline__ bool grid_sync(GridBar *bar, uint64_t limit_ticks)
+{
+    __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads and stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned g = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == gridDim.x) {
+            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                if (wall_clock64() - t0 > limit_ticks) {
+                    __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        s_ok = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__device__ __forceinline__ int ld32(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t ld64(const int64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ring[0..2]: per-round counters, round r uses ring[r % 3]; gc: global-relabel
+// counters and the phase results.
+template <int G>
+__global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseParams P, Ctl *ring,
+                                               Ctl *gc, GridBar *bar)
+{
+    MF_STAGE(stage);
+    constexpr int GPW = 64 / G;
+    const int n = g.n;
+    const int64_t m = g.slots;
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    const int grp = lane / G;
+    const int groups = blockDim.x / G;
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gthreads = gridDim.x * blockDim.x;
+    const int wave = gtid >> 6;
+    const int nwaves = gthreads >> 6;
+    const int sink = P.sink, other = P.other;
+    const RoundParams rp{P.beta, sink};
+
+    int64_t W = 0;
+    bool force = true;
+    int count = 0;
+    bool dense = false;
+    int32_t *A = st.A, *A2 = st.A2;
+    int64_t rounds = 0, grs = 0, levels = 0, dense_rounds = 0, bu_levels = 0;
+    int status = 0;
+
+    while (true) {
+        bool just = false;
+        if (force || P.freq_num * W > P.freq_den * (P.alpha * n + m)) {
+            // ---------------- global relabel ----------------
+            for (int v = gtid; v < n; v += gthreads) {
+                const int lab = v == sink ? 0 : n;
+                st.d[v] = lab;
+                st.dn[v] = lab;
+            }
+            if (gtid == 0) {
+                st.Q[0] = sink;
+                gc->nq[0] = 1;
+                gc->nq[1] = 0;
+                gc->nq[2] = 0;
+                gc->nh[0] = 0;
+                gc->nh[1] = 0;
+                gc->nh[2] = 0;
+                gc->na = 0;
+                gc->na2 = 0;
+            }
+            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            int level = 0;
+            int64_t nq = 1, unvisited = n - 2;
+            int32_t *qin = st.Q, *qout = st.Q2;
+            while (nq > 0) {
+                const int next = level + 1;
+                int32_t *qcount = &gc->nq[next % 3];
+                if (gtid == 0) {
+                    gc->nq[(level + 2) % 3] = 0;
+                    gc->nh[next % 3] = 0;
+                }
+                int64_t gslots = 0;
+                stage_init(stage);
+                if (nq * P.bu_factor > unvisited) {
+                    bu_levels++;
+                    // bottom-up: each unlabelled vertex looks for a neighbour of
+                    // label `level` through its own residual slots
+                    for (int base = blockIdx.x * blockDim.x; base < n; base += gthreads) {
+                        const int w = base + threadIdx.x;
+                        bool found = false;
+                        if (w < n && w != sink && w != other && st.d[w] == n) {
+                            const int beg = g.off[w], end = g.off[w + 1];
+                            for (int a = beg; a < end; a++) {
+                                gslots++;
+                                if (st.res[a] > 0 && st.d[g.head[a]] == level) {
+                                    found = true;
+                                    break;
+                                }
+                            }
+                            if (found) {
+                                st.d[w] = next;
+                                st.dn[w] = next;
+                            }
+                        }
+                        stage_append(stage, found, w, qout, qcount);
+                    }
+                    stage_flush(stage, qout, qcount);
+                } else {
+                    // top-down over the frontier list; hubs are set aside
+                    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nq; i += gridDim.x * groups) {
+                        const int v = qin[i];
+                        const int beg = g.off[v], end = g.off[v + 1];
+                        if (end - beg > P.hubdeg) {
+                            wave_append(gl == 0, v, st.H, &gc->nh[level % 3]);
+                            continue;
+                        }
+                        if (gl == 0) gslots += end - beg;
+                        for (int base = beg; base < end; base += G) {
+                            const int a = base + gl;
+                            bool claim = false;
+                            int w = 0;
+                            if (a < end) {
+                                w = g.head[a];
+                                if (w != sink && w != other && st.d[w] == n && st.res[g.rev[a]] > 0) {
+                                    if (atomicCAS(&st.d[w], n, next) == n) {
+                                        claim = true;
+                                        st.dn[w] = next;
+                                    }
+                                }
+                            }
+                            stage_append(stage, claim, w, qout, qcount);
+                        }
+                    }
+                    stage_flush(stage, qout, qcount);
+                    if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+                    const int nh = ld32(&gc->nh[level % 3]);
+                    if (nh > 0) {
+                        stage_init(stage);
+                        for (int h = 0; h < nh; h++) {
+                            const int v = st.H[h];
+                            const int beg = g.off[v], end = g.off[v + 1];
+                            if (gtid == 0) gslots += end - beg;
+                            for (int base = beg + blockIdx.x * blockDim.x; base < end; base += gthreads) {
+                                const int a = base + threadIdx.x;
+                                bool claim = false;
+                                int w = 0;
+                                if (a < end) {
+                                    w = g.head[a];
+                                    if (w != sink && w != other && st.d[w] == n && st.res[g.rev[a]] > 0) {
+                                        if (atomicCAS(&st.d[w], n, next) == n) {
+                                            claim = true;
+                                            st.dn[w] = next;
+                                        }
+                                    }
+                                }
+                                stage_append(stage, claim, w, qout, qcount);
+                            }
+                        }
+                        stage_flush(stage, qout, qcount);
+                    }
+                }
+                block_add64(gslots, &gc->gslots);
+                if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+                nq = ld32(qcount);
+                unvisited -= nq;
+                int32_t *tq = qin;
+                qin = qout;
+                qout = tq;
+                level = next;
+            }
+            levels += level - 1;
+            grs++;
+            // working set: every non-terminal vertex with excess and label < n
+            {
+                int cnt = 0;
+                for (int v = gtid; v < n; v += gthreads) {
+                    const bool p = v != sink && v != other && st.e[v] > 0 && st.d[v] < n;
+                    st.act[v] = p;
+                    cnt += p;
+                }
+                block_add32(cnt, &gc->na2);
+            }
+            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            count = ld32(&gc->na2);
+            dense = count > P.dense_threshold;
+            if (!dense && count > 0) {
+                stage_init(stage);
+                for (int base = blockIdx.x * blockDim.x; base < n; base += gthreads) {
+                    const int v = base + threadIdx.x;
+                    stage_append(stage, v < n && st.act[v], v, A, &gc->na);
+                }
+                stage_flush(stage, A, &gc->na);
+                if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            }
+            W = 0;
+            force = false;
+            just = true;
+        }
+        if (count == 0) {
+            if (just) break;           // a fresh global relabel found no active vertex
+            force = true;
+            continue;
+        }
+        if (P.max_rounds > 0 && rounds >= P.max_rounds) {
+            status = 1;
+            break;
+        }
+        // ---------------- one round ----------------
+        {
+            Ctl *rc = &ring[rounds % 3];
+            if (gtid == 0) {
+                Ctl *nx = &ring[(rounds + 1) % 3];
+                nx->nc = 0;
+                nx->na2 = 0;
+                nx->na = 0;
+                nx->work = 0;
+            }
+            StateView sr = st;
+            sr.ctl = rc;
+            sr.A = A;
+            sr.A2 = A2;
+            DisAcc dacc;
+            if (dense) dense_rounds++;
+            if (dense) {
+                for (int base = wave * 64; base < n; base += nwaves * 64) {
+                    const int v0 = base + lane;
+                    const uint64_t mask = __ballot(v0 < n && st.act[v0] != 0);
+                    const int cnt = __popcll(mask);
+                    for (int k0 = 0; k0 < cnt; k0 += GPW) {
+                        const int k = k0 + grp;
+                        if (k < cnt) discharge_vertex<G, true>(g, sr, rp, base + nth_set_bit(mask, k), gl, dacc);
+                    }
+                }
+            } else {
+                for (int i = blockIdx.x * groups + threadIdx.x / G; i < count; i += gridDim.x * groups)
+                    discharge_vertex<G, false>(g, sr, rp, A[i], gl, dacc);
+            }
+            discharge_flush(sr, rp, dacc);
+            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            MerAcc macc;
+            if (dense) {
+                for (int base = wave * 64; base < n; base += nwaves * 64) {
+                    const int v0 = base + lane;
+                    const uint64_t mask = __ballot(v0 < n && st.touched[v0] != 0);
+                    const int cnt = __popcll(mask);
+                    for (int k0 = 0; k0 < cnt; k0 += GPW) {
+                        const int k = k0 + grp;
+                        if (k < cnt) merge_vertex<G, true>(g, sr, base + nth_set_bit(mask, k), gl, sink, other, macc);
+                    }
+                }
+            } else {
+                const int nc = ld32(&rc->nc);
+                for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups) {
+                    const int w = st.C[i];
+                    if (st.owner[w] != i) continue;
+                    merge_vertex<G, false>(g, sr, w, gl, sink, other, macc);
+                }
+            }
+            merge_flush(sr, dense, macc);
+            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            const int nxt = ld32(&rc->na2);
+            W += ld64(&rc->work) + P.round_charge;
+            rounds++;
+            const bool was_dense = dense;
+            dense = nxt > P.dense_threshold;
+            if (!was_dense && !dense) {
+                int32_t *t = A;
+                A = A2;
+                A2 = t;
+            } else if (was_dense && !dense && nxt > 0) {
+                stage_init(stage);
+                for (int base = blockIdx.x * blockDim.x; base < n; base += gthreads) {
+                    const int v = base + threadIdx.x;
+                    stage_append(stage, v < n && st.act[v], v, A, &rc->na);
+                }
+                stage_flush(stage, A, &rc->na);
+                if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            }
+            count = nxt;
+        }
+    }
+    if (gtid == 0) {
+        gc->p_rounds = rounds;
+        gc->p_grs = grs;
+        gc->p_levels = levels;
+        gc->p_status = status;
+        gc->p_lists = A == st.A ? 0 : 1;
+        gc->p_dense_rounds = dense_rounds;
+        gc->p_bu_levels = bu_levels;
+    }
+    return;
+aborted:
+    if (gtid == 0) gc->p_status = 2;
+}
+
+// ---------------------------------------------------------------------------
+
+template <int G>
+static hipError_t launch_phase_t(int grid, GraphView g, StateView st, PhaseParams P, Ctl *ring, Ctl *gc,
+                                 GridBar *bar, hipStream_t s)
+{
+    void *args[] = {&g, &st, &P, &ring, &gc, &bar};
+    return hipLaunchCooperativeKernel((const void *)k_phase<G>, dim3(grid), dim3(256), args, 0, s);
+}
+
+template <int G>
+static int phase_blocks_per_cu_t()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_phase<G>, 256, 0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+#define MF_DISPATCH_G2(G, CALL)                   \
+    switch (G) {                                  \
+    case 1: return CALL(1);                       \
+    case 2: return CALL(2);                       \
+    case 4: return CALL(4);                       \
+    case 8: return CALL(8);                       \
+    case 16: return CALL(16);                     \
+    case 32: return CALL(32);                     \
+    default: return CALL(64);                     \
+    }
+
+hipError_t launch_phase(int G, int grid, GraphView g, StateView st, PhaseParams P, Ctl *ring, Ctl *gc,
+                        GridBar *bar, hipStream_t s)
+{
+#define C_(X) launch_phase_t<X>(grid, g, st, P, ring, gc, bar, s)
+    MF_DISPATCH_G2(G, C_)
+#undef C_
+}
+
+int phase_blocks_per_cu(int G)
+{
+#define C_(X) phase_blocks_per_cu_t<X>()
+    MF_DISPATCH_G2(G, C_)
+#undef C_
+}
+
+}  // namespace mf

@@ -51,6 +51,23 @@ void launch_side(GraphView g, const int32_t *d, uint8_t *side, int grid, hipStre
 void launch_cut(GraphView g, const uint8_t *side, Ctl *ctl, int grid, hipStream_t s);
 void launch_flow(GraphView g, const int32_t *res, int32_t *flow, int grid, hipStream_t s);
 void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s);
+
+struct GridBar {
+    unsigned count;
+    unsigned gen;
+    int abort;
+    int pad;
+};
+struct PhaseParams {
+    int sink, other;
+    int64_t freq_num, freq_den, alpha, beta, round_charge, max_rounds;
+    int64_t dense_threshold, bu_factor;
+    int hubdeg;
+    uint64_t limit_ticks;
+};
+hipError_t launch_phase(int G, int grid, GraphView g, StateView st, PhaseParams P, Ctl *ring, Ctl *gc,
+                        GridBar *bar, hipStream_t s);
+int phase_blocks_per_cu(int G);
 }  // namespace mf
 
 using namespace mf;
@@ -91,8 +108,10 @@ struct mf_context {
     size_t budget = 0;     // 0 = unbounded
     size_t used = 0;       // bytes held (graphs + workspace)
     hipStream_t stream = nullptr;
-    Ctl *ctl = nullptr;        // device
-    Ctl *ctl_host = nullptr;   // pinned host mirror
+    Ctl *ctl = nullptr;        // device: [0] main, [1..3] round ring, [4] global relabel (persistent)
+    Ctl *ctl_host = nullptr;   // pinned host mirror of all five
+    GridBar *bar = nullptr;    // device: persistent-kernel barrier
+    uint64_t wall_hz = 100000000ull;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipEvent_t pev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // profiling
     Workspace ws;
@@ -221,8 +240,13 @@ mf_status mf_context_create(int device, size_t hbm_budget_bytes, mf_context **ou
             st = fail(nullptr, MF_EDEVICE, "hipStreamCreate failed");
             break;
         }
-        if (hipMalloc((void **)&ctx->ctl, sizeof(Ctl)) != hipSuccess ||
-            hipHostMalloc((void **)&ctx->ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        int wall_khz = 0;
+        if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess &&
+            wall_khz > 0)
+            ctx->wall_hz = (uint64_t)wall_khz * 1000ull;
+        if (hipMalloc((void **)&ctx->ctl, 5 * sizeof(Ctl)) != hipSuccess ||
+            hipMalloc((void **)&ctx->bar, sizeof(GridBar)) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->ctl_host, 5 * sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
             st = fail(nullptr, MF_EDEVICE, "control block allocation failed");
             break;
         }
@@ -250,6 +274,7 @@ void mf_context_destroy(mf_context *ctx)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
+    if (ctx->bar) (void)hipFree(ctx->bar);
     if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
     for (auto ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -276,9 +301,10 @@ static const char *validation_message(int bits)
     return "invalid graph";
 }
 
-static mf_status read_ctl(mf_context *ctx)
+static mf_status read_ctl(mf_context *ctx, int count = 1)
 {
-    HIPCHK(ctx, hipMemcpyAsync(ctx->ctl_host, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ctl_host, ctx->ctl, count * sizeof(Ctl), hipMemcpyDeviceToHost,
+                               ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return MF_OK;
 }
@@ -458,9 +484,10 @@ struct Solve {
     int64_t bu_factor;         // bottom-up BFS level when frontier * bu_factor > unvisited
     int hubdeg;                // frontier vertices above this degree are expanded by the grid
     bool profile;
+    bool persistent;
     // profiling accumulators
-    double ms_dis = 0, ms_mer = 0, ms_gr = 0;
-    int64_t n_dis = 0, n_mer = 0, n_gr = 0;
+    double ms_dis = 0, ms_mer = 0, ms_gr = 0, ms_phase = 0;
+    int64_t n_dis = 0, n_mer = 0, n_gr = 0, n_phase = 0;
     int64_t dense_rounds = 0, bu_levels = 0, td_levels = 0, grs = 0;
 };
 
@@ -597,6 +624,64 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
     }
 }
 
+// One phase as a single persistent cooperative kernel.
+static mf_status run_phase_persistent(Solve &S, int sink, int other, int64_t max_rounds, PhaseStats &ps,
+                                      int64_t cum[8])
+{
+    mf_context *ctx = S.ctx;
+    const mf_options &o = S.opt;
+    HIPCHK(ctx, hipMemsetAsync(ctx->ctl + 1, 0, 4 * sizeof(Ctl), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(ctx->bar, 0, sizeof(GridBar), ctx->stream));
+    PhaseParams P;
+    P.sink = sink;
+    P.other = other;
+    P.freq_num = o.gr_freq_num;
+    P.freq_den = o.gr_freq_den;
+    P.alpha = o.gr_alpha;
+    P.beta = o.gr_beta;
+    P.round_charge = o.gr_round_charge;
+    P.max_rounds = max_rounds;
+    P.dense_threshold = S.dense_threshold;
+    P.bu_factor = S.bu_factor;
+    P.hubdeg = S.hubdeg;
+    P.limit_ticks = ctx->wall_hz * 30ull;      // 30 s: far above any single step
+    int per_cu = phase_blocks_per_cu(S.G);
+    if (per_cu <= 0) return fail(ctx, MF_EDEVICE, "occupancy query for the persistent kernel failed");
+    if (o.blocks_per_cu > 0) per_cu = std::min(per_cu, (int)o.blocks_per_cu);
+    const int grid = per_cu * ctx->num_cus;
+    if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[0], ctx->stream));
+    hipError_t e = launch_phase(S.G, grid, S.g, S.st, P, ctx->ctl + 1, ctx->ctl + 4, ctx->bar, ctx->stream);
+    if (e != hipSuccess)
+        return fail(ctx, MF_EDEVICE, "persistent kernel launch failed: %s", hipGetErrorString(e));
+    if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[1], ctx->stream));
+    mf_status st = read_ctl(ctx, 5);
+    if (st != MF_OK) return st;
+    if (S.profile) {
+        S.ms_phase += elapsed(ctx->pev[0], ctx->pev[1]);
+        S.n_phase++;
+    }
+    const Ctl *h = ctx->ctl_host;
+    const Ctl &gc = h[4];
+    if (gc.p_status == 2) return fail(ctx, MF_EDEVICE, "persistent kernel barrier timed out");
+    ps.rounds += gc.p_rounds;
+    ps.grs += gc.p_grs;
+    ps.levels += gc.p_levels;
+    S.dense_rounds += gc.p_dense_rounds;
+    S.bu_levels += gc.p_bu_levels;
+    S.grs += gc.p_grs;
+    for (int i = 1; i <= 3; i++) {
+        cum[0] += h[i].pushes;
+        cum[1] += h[i].relabels;
+        cum[2] += h[i].scans;
+        cum[3] += h[i].dverts;
+        cum[4] += h[i].dslots;
+        cum[5] += h[i].mverts;
+        cum[6] += h[i].mslots;
+    }
+    cum[7] += gc.gslots;
+    return gc.p_status == 1 ? MF_ETIMEOUT : MF_OK;
+}
+
 static mf_status check_options(mf_context *ctx, const mf_options *o)
 {
     if (o->gr_freq_den <= 0 || o->gr_freq_num < 0 || o->gr_alpha < 0 || o->gr_beta < 0 ||
@@ -650,10 +735,12 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.Gm = o.lanes_per_merge > 0 ? pick_lanes(o.lanes_per_merge, 1, 1) : S.G;
     S.maxgrid = ctx->num_cus * 16;
     S.avg_deg_ceil = (dg->slots + dg->n - 1) / std::max<int64_t>(1, dg->n);
-    S.dense_threshold = std::max<int64_t>(4096, dg->n / 64);
+    S.dense_threshold = std::min<int64_t>(65536, std::max<int64_t>(2048, dg->n / 512));
     S.bu_factor = 8;
     S.hubdeg = 64 * S.G;
     S.profile = (o.flags & MF_PROFILE) != 0;
+    S.persistent = (o.flags & MF_PERSISTENT) != 0;
+    if (o.dense_threshold > 0) S.dense_threshold = o.dense_threshold;
 
     const int n = dg->n;
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
@@ -663,13 +750,15 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, grid_for(n, 256 / S.Gm, S.maxgrid), ctx->stream);
 
     PhaseStats p1;
-    mf_status ph = run_phase(S, dg->t, dg->s, o.max_rounds, p1);
+    int64_t cum[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // persistent-mode counters
+    mf_status ph = S.persistent ? run_phase_persistent(S, dg->t, dg->s, o.max_rounds, p1, cum)
+                                : run_phase(S, dg->t, dg->s, o.max_rounds, p1);
     if (ph != MF_OK && ph != MF_ETIMEOUT) return ph;
     const bool timed_out = ph == MF_ETIMEOUT;
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
     if ((st = read_ctl(ctx)) != MF_OK) return st;
-    const int64_t pushes = ctx->ctl_host->pushes, relabels = ctx->ctl_host->relabels,
-                  scans = ctx->ctl_host->scans;
+    const int64_t pushes = ctx->ctl_host->pushes + cum[0], relabels = ctx->ctl_host->relabels + cum[1],
+                  scans = ctx->ctl_host->scans + cum[2];
 
     // value, sink side and cut capacity of the maximum preflow (the labels are
     // exact distances to t here)
@@ -683,7 +772,8 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
 
     PhaseStats p2;
     if (!preflow_only && !timed_out) {
-        ph = run_phase(S, dg->s, dg->t, 0, p2);
+        ph = S.persistent ? run_phase_persistent(S, dg->s, dg->t, 0, p2, cum)
+                          : run_phase(S, dg->s, dg->t, 0, p2);
         if (ph != MF_OK) return ph;
     }
     if (flow_dev) launch_flow(S.g, w.res, flow_dev, grid_for(dg->slots, 256, S.maxgrid), ctx->stream);
@@ -723,7 +813,15 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
             //  global relabel: 12 B per slot examined (head, reverse index,
             //    residual, label), 9 B per vertex per relabel (labels reset,
             //    working-set rebuild) and 4 B per vertex per bottom-up level.
-            const Ctl &c = *ctx->ctl_host;
+            Ctl c = *ctx->ctl_host;
+            c.pushes += cum[0];
+            c.dverts += cum[3];
+            c.dslots += cum[4];
+            c.mverts += cum[5];
+            c.mslots += cum[6];
+            c.gslots += cum[7];
+            stats->ms_phase_kernel = S.ms_phase;
+            stats->phase_launches = S.n_phase;
             stats->ms_discharge = S.ms_dis;
             stats->ms_merge = S.ms_mer;
             stats->ms_global_relabel = S.ms_gr;

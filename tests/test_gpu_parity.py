@@ -35,11 +35,11 @@ def _note(msg):
     sys.stdout.flush()
 
 
-def _compare(ctx, g, sched=None, lanes=0, check_a=True):
+def _compare(ctx, g, sched=None, lanes=0, check_a=True, **extra):
     import paper_1507_01926_amd as mf
     sched = dict(sched or {})
-    opt = mf.options(lanes_per_vertex=lanes, **{("gr_" + k if not k.startswith("gr_") else k): v
-                                                 for k, v in sched.items()})
+    opt = mf.options(lanes_per_vertex=lanes, **extra, **{("gr_" + k if not k.startswith("gr_") else k): v
+                                                          for k, v in sched.items()})
     osched = {k.replace("gr_", "").replace("freq_num", "freq_num"): v for k, v in sched.items()}
     r = ctx.solve(g, opt)
     B = oracle.sync_maxflow(g, schedule=osched)
@@ -188,3 +188,28 @@ def test_device_entry_point_with_torch_buffers(ctx):
     assert r["value"] == B["value"]
     assert (flow.cpu().numpy().astype(np.int64) == B["flow"]).all()
     assert (side.cpu().numpy() == B["tstar"]).all()
+
+
+@pytest.mark.parametrize("name,f", [("c1", 1), ("c2", 16), ("c3", 8), ("c4a", 32), ("c4b", 16)])
+def test_persistent_mode_matches(ctx, name, f):
+    """Each phase as one persistent cooperative kernel gives the same results
+    as one launch per round and level (both must equal the oracle bit for bit)."""
+    g = make_config(name, f)
+    _note(f"persistent {name}/{f}")
+    _compare(ctx, g, persistent=True, check_a=False)
+    _compare(ctx, g, persistent=True, check_a=False, sched=dict(round_charge=20000))
+
+
+@pytest.mark.parametrize("dense_threshold", [1, 64, 1 << 30])
+def test_dense_threshold_does_not_change_results(ctx, dense_threshold):
+    g = make_config("c2", 8)
+    _note(f"dense_threshold={dense_threshold}")
+    _compare(ctx, g, dense_threshold=dense_threshold, check_a=False)
+    _compare(ctx, g, dense_threshold=dense_threshold, check_a=False, persistent=True)
+
+
+@pytest.mark.parametrize("bpc", [1, 2])
+def test_persistent_grid_size(ctx, bpc):
+    g = make_config("c4a", 16)
+    _note(f"blocks_per_cu={bpc}")
+    _compare(ctx, g, blocks_per_cu=bpc, check_a=False, persistent=True)
