@@ -168,6 +168,36 @@ mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, const mf_optio
                           int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
                           mf_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Batched solver (many instances of uneven size in one launch).
+ *
+ * Every instance is solved completely by one workgroup of a persistent
+ * kernel that takes instances from a queue; instances are grouped by their
+ * lane count (one kernel per group, on separate streams, captured together in
+ * one hipGraph).  Results are identical to mf_solve's for the same options.
+ */
+typedef struct {
+    int32_t status;              /* mf_status of this instance */
+    int32_t lanes_per_vertex;    /* lane count used */
+    int64_t value, cut_capacity;
+    int64_t rounds, rounds2, global_relabels, global_relabels2, bfs_levels;
+    int64_t pushes, relabels;
+    double ms_start, ms_end;     /* device time of the instance's start and end, from the
+                                    first instance's start */
+} mf_result;
+
+/* Solves k graphs given in host memory.  opts is NULL (the defaults for all)
+ * or an array of k options (per-instance schedules, e.g. from the autotuner;
+ * lanes_per_vertex 0 = automatic, otherwise 4, 8, 16 or 32).  flows[i] /
+ * sides[i] are host buffers (int32[slots_i] / uint8[n_i]) or NULL, and flows
+ * or sides may themselves be NULL.  An invalid graph gets MF_EINVAL in its
+ * result and does not stop the others.  The whole batch must fit the HBM
+ * budget (MF_ENOMEM otherwise).  stats (may be NULL) receives ms_total of the
+ * batch launch. */
+mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *graphs, const mf_options *opts,
+                         int32_t *const *flows, uint8_t *const *sides, mf_result *results,
+                         mf_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

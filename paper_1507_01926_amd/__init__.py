@@ -58,6 +58,13 @@ class mf_stats(ctypes.Structure):
         ("ms_phase_kernel", ctypes.c_double), ("phase_launches", ctypes.c_int64)]
 
 
+class mf_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("lanes_per_vertex", ctypes.c_int32)] + [
+        (k, ctypes.c_int64) for k in ("value", "cut_capacity", "rounds", "rounds2", "global_relabels",
+                                      "global_relabels2", "bfs_levels", "pushes", "relabels")] + [
+        ("ms_start", ctypes.c_double), ("ms_end", ctypes.c_double)]
+
+
 _LIB = None
 
 # (name, restype, argtypes) of every symbol include/maxflow.h declares
@@ -74,6 +81,7 @@ SIGNATURES = [
     ("mf_solve_uploaded", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve_device", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("mf_batch_solve", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
 ]
 
 
@@ -216,6 +224,37 @@ class Context:
         out = _stats_dict(stats)
         out.update(value=int(val.value))
         return out
+
+
+def _result_dict(r: mf_result) -> dict:
+    return {k: getattr(r, k) for k, _ in mf_result._fields_}
+
+
+def batch_solve(ctx: "Context", graphs, opts=None, want_flow=True, want_side=True):
+    """mf_batch_solve over host graphs; opts: None or one mf_options per graph."""
+    k = len(graphs)
+    hgs = [_HostGraph(g) for g in graphs]
+    garr = (mf_graph * k)(*[h.st for h in hgs])
+    oarr = None
+    if opts is not None:
+        oarr = (mf_options * k)(*opts)
+    flows = [np.zeros(max(1, h.head.shape[0]), dtype=np.int32) if want_flow else None for h in hgs]
+    if opts is not None:
+        flows = [None if (o.flags & MF_PREFLOW_ONLY) else f for f, o in zip(flows, opts)]
+    sides = [np.zeros(g.n, dtype=np.uint8) if want_side else None for g in graphs]
+    fptrs = (ctypes.c_void_p * k)(*[None if f is None else f.ctypes.data for f in flows])
+    sptrs = (ctypes.c_void_p * k)(*[None if x is None else x.ctypes.data for x in sides])
+    res = (mf_result * k)()
+    stats = mf_stats()
+    st = lib().mf_batch_solve(ctx.h, k, garr, oarr, fptrs, sptrs, res, ctypes.byref(stats))
+    ctx._check(st)
+    out = []
+    for i in range(k):
+        d = _result_dict(res[i])
+        d["flow"] = None if flows[i] is None else flows[i][: hgs[i].head.shape[0]]
+        d["sink_side"] = sides[i]
+        out.append(d)
+    return out, stats.ms_total
 
 
 class DeviceGraph:

@@ -1,0 +1,56 @@
+// Structures shared by the persistent / batched kernels and the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mf_device.h"
+
+namespace mf {
+
+struct GridBar {
+    unsigned count;
+    unsigned gen;
+    int abort;
+    int pad;
+};
+
+struct PhaseParams {
+    int sink, other;
+    int64_t freq_num, freq_den, alpha, beta, round_charge, max_rounds;
+    int64_t dense_threshold, bu_factor;
+    int hubdeg;
+    uint64_t limit_ticks;    // grid-barrier wait limit in wall-clock ticks
+};
+
+// One instance of a batch (device memory).
+struct BatchItem {
+    GraphView g;
+    StateView st;          // st.ctl unused
+    Ctl *ctl;              // [5]: [0] outputs, [1..3] round ring, [4] global relabel
+    int32_t *flow;         // [slots] or null
+    uint8_t *side;         // [n] or null (then st.touched is used as scratch)
+    PhaseParams p;         // schedule; sink / other are set per phase
+    int32_t G;             // lanes per vertex: 4, 8, 16 or 32
+    int32_t preflow_only;
+};
+
+struct BatchResult {
+    int64_t value, cut, rounds, rounds2, grs, grs2, levels, pushes, relabels;
+    int64_t t_start, t_end;          // wall-clock ticks
+    int32_t status, block;
+};
+
+struct BatchQueue {
+    int32_t next;     // next position of `order` to hand out
+    int32_t count;    // number of positions
+};
+
+hipError_t launch_phase(int G, int grid, GraphView g, StateView st, PhaseParams P, Ctl *ring, Ctl *gc,
+                        GridBar *bar, hipStream_t s);
+int phase_blocks_per_cu(int G);
+hipError_t launch_batch(int G, int grid, const BatchItem *items, const int32_t *order, BatchResult *results,
+                        BatchQueue *q, hipStream_t s);
+void launch_queue_init(BatchQueue *q, int count, hipStream_t s);
+int batch_blocks_per_cu(int G);
+
+}  // namespace mf

@@ -10,24 +10,12 @@
 // flag, every block leaves at its next barrier, and the host reports a
 // device error.
 #include "mf_device.h"
+#include "mf_phase.h"
 #include "mf_steps.h"
 
 namespace mf {
 
-struct GridBar {
-    unsigned count;
-    unsigned gen;
-    int abort;
-    int pad;
-};
 
-struct PhaseParams {
-    int sink, other;
-    int64_t freq_num, freq_den, alpha, beta, round_charge, max_rounds;
-    int64_t dense_threshold, bu_factor;
-    int hubdeg;
-    uint64_t limit_ticks;    // barrier wait limit in wall-clock ticks
-};
 
 // Memory ordering: every wave waits for its own outstanding stores before the
 // block barrier; thread 0 then releases the block's writes to device scope
@@ -74,13 +62,33 @@ __device__ __forceinline__ int64_t ld64(const int64_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+struct GridTeam {
+    GridBar *bar;
+    uint64_t limit_ticks;
+    __device__ int brank() const { return blockIdx.x; }
+    __device__ int nblocks() const { return gridDim.x; }
+    __device__ bool sync() { return grid_sync(bar, limit_ticks); }
+};
+
+struct BlockTeam {
+    __device__ int brank() const { return 0; }
+    __device__ int nblocks() const { return 1; }
+    __device__ bool sync()
+    {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        return true;
+    }
+};
+
+// One phase of the solve run by a team of threads: the whole grid (GridTeam,
+// grid barriers) or one block (BlockTeam, block barriers).
 // ring[0..2]: per-round counters, round r uses ring[r % 3]; gc: global-relabel
-// counters and the phase results.
-template <int G>
-__global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseParams P, Ctl *ring,
-                                               Ctl *gc, GridBar *bar)
+// counters and the phase results.  Returns 0 done, 1 round limit, 2 aborted.
+template <int G, class Team>
+__device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const StateView &st,
+                              const PhaseParams &P, Ctl *ring, Ctl *gc)
 {
-    MF_STAGE(stage);
     constexpr int GPW = 64 / G;
     const int n = g.n;
     const int64_t m = g.slots;
@@ -88,8 +96,9 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
     const int gl = lane & (G - 1);
     const int grp = lane / G;
     const int groups = blockDim.x / G;
-    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int gthreads = gridDim.x * blockDim.x;
+    const int brank = tm.brank(), nblocks = tm.nblocks();
+    const int gtid = brank * blockDim.x + threadIdx.x;
+    const int gthreads = nblocks * blockDim.x;
     const int wave = gtid >> 6;
     const int nwaves = gthreads >> 6;
     const int sink = P.sink, other = P.other;
@@ -123,7 +132,7 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                 gc->na = 0;
                 gc->na2 = 0;
             }
-            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            if (!tm.sync()) goto aborted;
             int level = 0;
             int64_t nq = 1, unvisited = n - 2;
             int32_t *qin = st.Q, *qout = st.Q2;
@@ -140,7 +149,7 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                     bu_levels++;
                     // bottom-up: each unlabelled vertex looks for a neighbour of
                     // label `level` through its own residual slots
-                    for (int base = blockIdx.x * blockDim.x; base < n; base += gthreads) {
+                    for (int base = brank * blockDim.x; base < n; base += gthreads) {
                         const int w = base + threadIdx.x;
                         bool found = false;
                         if (w < n && w != sink && w != other && st.d[w] == n) {
@@ -162,7 +171,7 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                     stage_flush(stage, qout, qcount);
                 } else {
                     // top-down over the frontier list; hubs are set aside
-                    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nq; i += gridDim.x * groups) {
+                    for (int i = brank * groups + threadIdx.x / G; i < nq; i += nblocks * groups) {
                         const int v = qin[i];
                         const int beg = g.off[v], end = g.off[v + 1];
                         if (end - beg > P.hubdeg) {
@@ -187,7 +196,7 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                         }
                     }
                     stage_flush(stage, qout, qcount);
-                    if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+                    if (!tm.sync()) goto aborted;
                     const int nh = ld32(&gc->nh[level % 3]);
                     if (nh > 0) {
                         stage_init(stage);
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                             const int v = st.H[h];
                             const int beg = g.off[v], end = g.off[v + 1];
                             if (gtid == 0) gslots += end - beg;
-                            for (int base = beg + blockIdx.x * blockDim.x; base < end; base += gthreads) {
+                            for (int base = beg + brank * blockDim.x; base < end; base += gthreads) {
                                 const int a = base + threadIdx.x;
                                 bool claim = false;
                                 int w = 0;
@@ -215,7 +224,7 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                     }
                 }
                 block_add64(gslots, &gc->gslots);
-                if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+                if (!tm.sync()) goto aborted;
                 nq = ld32(qcount);
                 unvisited -= nq;
                 int32_t *tq = qin;
@@ -235,17 +244,17 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                 }
                 block_add32(cnt, &gc->na2);
             }
-            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            if (!tm.sync()) goto aborted;
             count = ld32(&gc->na2);
             dense = count > P.dense_threshold;
             if (!dense && count > 0) {
                 stage_init(stage);
-                for (int base = blockIdx.x * blockDim.x; base < n; base += gthreads) {
+                for (int base = brank * blockDim.x; base < n; base += gthreads) {
                     const int v = base + threadIdx.x;
                     stage_append(stage, v < n && st.act[v], v, A, &gc->na);
                 }
                 stage_flush(stage, A, &gc->na);
-                if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+                if (!tm.sync()) goto aborted;
             }
             W = 0;
             force = false;
@@ -287,11 +296,11 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                     }
                 }
             } else {
-                for (int i = blockIdx.x * groups + threadIdx.x / G; i < count; i += gridDim.x * groups)
+                for (int i = brank * groups + threadIdx.x / G; i < count; i += nblocks * groups)
                     discharge_vertex<G, false>(g, sr, rp, A[i], gl, dacc);
             }
             discharge_flush(sr, rp, dacc);
-            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            if (!tm.sync()) goto aborted;
             MerAcc macc;
             if (dense) {
                 for (int base = wave * 64; base < n; base += nwaves * 64) {
@@ -305,14 +314,14 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                 }
             } else {
                 const int nc = ld32(&rc->nc);
-                for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups) {
+                for (int i = brank * groups + threadIdx.x / G; i < nc; i += nblocks * groups) {
                     const int w = st.C[i];
                     if (st.owner[w] != i) continue;
                     merge_vertex<G, false>(g, sr, w, gl, sink, other, macc);
                 }
             }
             merge_flush(sr, dense, macc);
-            if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+            if (!tm.sync()) goto aborted;
             const int nxt = ld32(&rc->na2);
             W += ld64(&rc->work) + P.round_charge;
             rounds++;
@@ -324,12 +333,12 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
                 A2 = t;
             } else if (was_dense && !dense && nxt > 0) {
                 stage_init(stage);
-                for (int base = blockIdx.x * blockDim.x; base < n; base += gthreads) {
+                for (int base = brank * blockDim.x; base < n; base += gthreads) {
                     const int v = base + threadIdx.x;
                     stage_append(stage, v < n && st.act[v], v, A, &rc->na);
                 }
                 stage_flush(stage, A, &rc->na);
-                if (!grid_sync(bar, P.limit_ticks)) goto aborted;
+                if (!tm.sync()) goto aborted;
             }
             count = nxt;
         }
@@ -343,9 +352,202 @@ __global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseP
         gc->p_dense_rounds = dense_rounds;
         gc->p_bu_levels = bu_levels;
     }
-    return;
+    return status;
 aborted:
     if (gtid == 0) gc->p_status = 2;
+    return 2;
+}
+
+
+template <int G>
+__global__ __launch_bounds__(256) void k_phase(GraphView g, StateView st, PhaseParams P, Ctl *ring,
+                                               Ctl *gc, GridBar *bar)
+{
+    MF_STAGE(stage);
+    GridTeam tm{bar, P.limit_ticks};
+    run_phase_team<G>(tm, stage, g, st, P, ring, gc);
+}
+
+// ---------------------------------------------------------------------------
+// Batched solver: one persistent launch over a table of instances; each block
+// takes the next instance from a queue and solves it completely (init,
+// saturation, phase 1, value / sink side / cut, phase 2, flow) with block
+// barriers only, so instances of any mix of sizes run side by side.
+
+
+
+
+__device__ void zero_ctls(Ctl *c, int k)
+{
+    int32_t *w = (int32_t *)c;
+    const int words = k * (int)(sizeof(Ctl) / sizeof(int32_t));
+    for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
+}
+
+template <int G>
+__device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *out, int32_t *sbuf,
+                                            int32_t *scnt, int32_t *sbase)
+{
+    constexpr int GPW = 64 / G;
+    Stage stage{sbuf, scnt, sbase};
+    BlockTeam tm;
+    const GraphView g = it.g;
+    StateView st = it.st;
+    Ctl *ctl = it.ctl;
+    const int n = g.n;
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    const int grp = lane / G;
+    zero_ctls(ctl, 5);
+    st.ctl = ctl;
+    // Listing 1 initialisation and saturation of the arcs out of s
+    for (int a = threadIdx.x; a < g.slots; a += blockDim.x) {
+        st.res[a] = g.cap[a];
+        st.delta[a] = 0;
+    }
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+        const int lab = v == g.s ? n : 0;
+        st.d[v] = lab;
+        st.dn[v] = lab;
+        st.e[v] = 0;
+        st.act[v] = 0;
+        st.touched[v] = 0;
+    }
+    tm.sync();
+    {
+        int64_t to_sink = 0;
+        for (int a = g.off[g.s] + threadIdx.x; a < g.off[g.s + 1]; a += blockDim.x) {
+            const int c = g.cap[a];
+            if (c <= 0) continue;
+            const int w = g.head[a];
+            st.res[a] = 0;
+            if (w == g.t) {
+                st.res[g.rev[a]] += c;
+                to_sink += c;
+            } else {
+                st.delta[g.rev[a]] = c;
+                st.touched[w] = 1;
+            }
+        }
+        block_add64(to_sink, &st.e[g.t]);
+    }
+    tm.sync();
+    {
+        MerAcc macc;
+        for (int base = (threadIdx.x >> 6) * 64; base < n; base += blockDim.x) {
+            const int v0 = base + lane;
+            const uint64_t mask = __ballot(v0 < n && st.touched[v0] != 0);
+            const int cnt = __popcll(mask);
+            for (int k0 = 0; k0 < cnt; k0 += GPW) {
+                const int k = k0 + grp;
+                if (k < cnt) merge_vertex<G, true>(g, st, base + nth_set_bit(mask, k), gl, g.t, g.s, macc);
+            }
+        }
+        merge_flush(st, true, macc);
+    }
+    tm.sync();
+    PhaseParams P = it.p;
+    P.sink = g.t;
+    P.other = g.s;
+    int status = run_phase_team<G>(tm, stage, g, st, P, ctl + 1, ctl + 4);
+    tm.sync();
+    BatchResult r{};
+    r.rounds = ctl[4].p_rounds;
+    r.grs = ctl[4].p_grs;
+    r.levels = ctl[4].p_levels;
+    // value, sink side (exact labels of the last global relabel) and cut capacity
+    uint8_t *side = it.side ? it.side : st.touched;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) side[v] = st.d[v] < n ? 1 : 0;
+    tm.sync();
+    {
+        int64_t cut = 0;
+        for (int a = threadIdx.x; a < g.slots; a += blockDim.x)
+            if (side[g.head[a]] && !side[g.head[g.rev[a]]]) cut += g.cap[a];
+        block_add64(cut, &ctl[0].cut);
+    }
+    tm.sync();
+    r.value = st.e[g.t];
+    r.cut = ctl[0].cut;
+    for (int i = 1; i <= 3; i++) {
+        r.pushes += ctl[i].pushes;
+        r.relabels += ctl[i].relabels;
+    }
+    if (!it.preflow_only && status == 0) {
+        tm.sync();
+        zero_ctls(ctl + 1, 4);
+        tm.sync();
+        P.sink = g.s;
+        P.other = g.t;
+        status = run_phase_team<G>(tm, stage, g, st, P, ctl + 1, ctl + 4);
+        tm.sync();
+        r.rounds2 = ctl[4].p_rounds;
+        r.grs2 = ctl[4].p_grs;
+        if (it.flow)
+            for (int a = threadIdx.x; a < g.slots; a += blockDim.x) it.flow[a] = g.cap[a] - st.res[a];
+    }
+    r.status = status;
+    tm.sync();
+    if (threadIdx.x == 0) {
+        r.t_end = wall_clock64();
+        r.t_start = out->t_start;
+        r.block = blockIdx.x;
+        *out = r;
+    }
+}
+
+// One launch per lane count G: items[order[0 .. count)] are the instances of
+// this launch.
+template <int G>
+__global__ __launch_bounds__(256) void k_batch(const BatchItem *items, const int32_t *order,
+                                               BatchResult *results, BatchQueue *q)
+{
+    __shared__ int32_t sbuf[STAGE_CAP];
+    __shared__ int32_t scnt, sbase;
+    __shared__ int s_i;
+    const int count = q->count;
+    while (true) {
+        if (threadIdx.x == 0) s_i = atomicAdd(&q->next, 1);
+        __syncthreads();
+        const int j = s_i;
+        __syncthreads();
+        if (j >= count) break;
+        const int i = order[j];
+        if (threadIdx.x == 0) results[i].t_start = wall_clock64();
+        solve_block<G>(items[i], &results[i], sbuf, &scnt, &sbase);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch(int G, int grid, const BatchItem *items, const int32_t *order, BatchResult *results,
+                        BatchQueue *q, hipStream_t s)
+{
+    switch (G) {
+    case 4: hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
+    case 8: hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
+    case 16: hipLaunchKernelGGL(k_batch<16>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
+    default: hipLaunchKernelGGL(k_batch<32>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_queue_init(BatchQueue *q, int count)
+{
+    q->next = 0;
+    q->count = count;
+}
+
+void launch_queue_init(BatchQueue *q, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue_init, dim3(1), dim3(1), 0, s, q, count);
+}
+
+int batch_blocks_per_cu(int G)
+{
+    int nb = 0;
+    const void *f = G == 4 ? (const void *)k_batch<4> : G == 8 ? (const void *)k_batch<8>
+                  : G == 16 ? (const void *)k_batch<16> : (const void *)k_batch<32>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess) return 0;
+    return nb;
 }
 
 // ---------------------------------------------------------------------------

@@ -25,6 +25,7 @@
 
 #include "../../include/maxflow.h"
 #include "mf_device.h"
+#include "mf_phase.h"
 
 namespace mf {
 void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid,
@@ -52,22 +53,7 @@ void launch_cut(GraphView g, const uint8_t *side, Ctl *ctl, int grid, hipStream_
 void launch_flow(GraphView g, const int32_t *res, int32_t *flow, int grid, hipStream_t s);
 void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s);
 
-struct GridBar {
-    unsigned count;
-    unsigned gen;
-    int abort;
-    int pad;
-};
-struct PhaseParams {
-    int sink, other;
-    int64_t freq_num, freq_den, alpha, beta, round_charge, max_rounds;
-    int64_t dense_threshold, bu_factor;
-    int hubdeg;
-    uint64_t limit_ticks;
-};
-hipError_t launch_phase(int G, int grid, GraphView g, StateView st, PhaseParams P, Ctl *ring, Ctl *gc,
-                        GridBar *bar, hipStream_t s);
-int phase_blocks_per_cu(int G);
+
 }  // namespace mf
 
 using namespace mf;
@@ -114,6 +100,8 @@ struct mf_context {
     uint64_t wall_hz = 100000000ull;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipEvent_t pev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // profiling
+    hipStream_t bstream[4] = {nullptr, nullptr, nullptr, nullptr};                 // batch groups
+    hipEvent_t bev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     Workspace ws;
     int num_cus = 256;
     std::string err;
@@ -280,6 +268,10 @@ void mf_context_destroy(mf_context *ctx)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : ctx->pev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto ev : ctx->bev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto bs : ctx->bstream)
+        if (bs) (void)hipStreamDestroy(bs);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -682,6 +674,15 @@ static mf_status run_phase_persistent(Solve &S, int sink, int other, int64_t max
     return gc.p_status == 1 ? MF_ETIMEOUT : MF_OK;
 }
 
+static mf_status ensure_batch_streams(mf_context *ctx)
+{
+    for (auto &bs : ctx->bstream)
+        if (!bs) HIPCHK(ctx, hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+    for (auto &ev : ctx->bev)
+        if (!ev) HIPCHK(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    return MF_OK;
+}
+
 static mf_status check_options(mf_context *ctx, const mf_options *o)
 {
     if (o->gr_freq_den <= 0 || o->gr_freq_num < 0 || o->gr_alpha < 0 || o->gr_beta < 0 ||
@@ -877,4 +878,304 @@ extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_
     dfree(ctx, side_dev, N);
     mf_graph_free(ctx, dg);
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solver (host side)
+
+namespace {
+
+struct InstLayout {
+    size_t off, head, rev, cap, res, delta, C, d, dn, owner, A, A2, Q, Q2, H, e, act, touched, side, flow;
+    size_t end;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+InstLayout layout_for(size_t base, int64_t n, int64_t S, bool want_flow)
+{
+    InstLayout L;
+    size_t p = base;
+    auto take = [&](size_t bytes) {
+        size_t at = p;
+        p = align256(p + std::max<size_t>(bytes, 4));
+        return at;
+    };
+    L.off = take(4 * (n + 1));
+    L.head = take(4 * S);
+    L.rev = take(4 * S);
+    L.cap = take(4 * S);
+    L.res = take(4 * S);
+    L.delta = take(4 * S);
+    L.C = take(4 * (S + n));
+    L.d = take(4 * n);
+    L.dn = take(4 * n);
+    L.owner = take(4 * n);
+    L.A = take(4 * n);
+    L.A2 = take(4 * n);
+    L.Q = take(4 * n);
+    L.Q2 = take(4 * n);
+    L.H = take(4 * n);
+    L.e = take(8 * n);
+    L.act = take(n);
+    L.touched = take(n);
+    L.side = take(n);
+    L.flow = want_flow ? take(4 * S) : 0;
+    L.end = p;
+    return L;
+}
+
+int batch_lanes(int requested, int64_t n, int64_t S)
+{
+    int G = requested;
+    if (G <= 0) {
+        const double avg = n > 0 ? (double)S / (double)n : 1.0;
+        G = 4;
+        while (G < avg && G < 32) G <<= 1;
+    }
+    if (G <= 4) return 4;
+    if (G <= 8) return 8;
+    if (G <= 16) return 16;
+    return 32;
+}
+
+}  // namespace
+
+extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *graphs, const mf_options *opts,
+                                    int32_t *const *flows, uint8_t *const *sides, mf_result *results,
+                                    mf_stats *stats)
+{
+    if (!ctx || k < 0 || (k > 0 && (!graphs || !results))) return fail(ctx, MF_EINVAL, "NULL argument");
+    if (k == 0) return MF_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    memset(results, 0, sizeof(mf_result) * (size_t)k);
+    std::vector<mf_options> o((size_t)k);
+    std::vector<char> ok((size_t)k, 1);
+    std::vector<InstLayout> lay((size_t)k);
+    size_t total = 0;
+    int64_t max_n = 0, max_S = 0;
+    for (int i = 0; i < k; i++) {
+        if (opts) o[i] = opts[i]; else mf_options_default(&o[i]);
+        const mf_graph &g = graphs[i];
+        results[i].status = MF_OK;
+        bool good = g.n >= 2 && g.slots >= 0 && g.slots < 2147483647LL && (int64_t)g.n + g.slots < 2147483647LL &&
+                    g.s >= 0 && g.s < g.n && g.t >= 0 && g.t < g.n && g.s != g.t && g.offsets &&
+                    (g.slots == 0 || (g.head && g.rev && g.cap)) && check_options(ctx, &o[i]) == MF_OK;
+        if (good && (o[i].flags & MF_PREFLOW_ONLY) && flows && flows[i]) good = false;
+        if (!good) {
+            ok[i] = 0;
+            results[i].status = MF_EINVAL;
+            continue;
+        }
+        lay[i] = layout_for(total, g.n, g.slots, flows && flows[i]);
+        total = lay[i].end;
+        max_n = std::max<int64_t>(max_n, g.n);
+        max_S = std::max<int64_t>(max_S, g.slots);
+    }
+    // device memory: arena, per-instance control blocks, items, results, queues, staging
+    uint8_t *arena = nullptr;
+    Ctl *ctls = nullptr;
+    BatchItem *items_d = nullptr;
+    BatchResult *res_d = nullptr;
+    BatchQueue *q_d = nullptr;
+    int32_t *order_d = nullptr;
+    int64_t *stage64 = nullptr;
+    const size_t ctl_bytes = sizeof(Ctl) * 5 * (size_t)k;
+    const size_t stage_bytes = 8 * (size_t)(max_n + 1 + max_S);
+    mf_status st = MF_OK;
+    auto release = [&]() {
+        dfree(ctx, arena, total);
+        dfree(ctx, ctls, ctl_bytes);
+        dfree(ctx, items_d, sizeof(BatchItem) * (size_t)k);
+        dfree(ctx, res_d, sizeof(BatchResult) * (size_t)k);
+        dfree(ctx, q_d, sizeof(BatchQueue) * 4);
+        dfree(ctx, order_d, 4 * (size_t)k);
+        dfree(ctx, stage64, stage_bytes);
+    };
+    if ((st = dalloc(ctx, (void **)&arena, total)) != MF_OK || (st = dalloc(ctx, (void **)&ctls, ctl_bytes)) != MF_OK ||
+        (st = dalloc(ctx, (void **)&items_d, sizeof(BatchItem) * (size_t)k)) != MF_OK ||
+        (st = dalloc(ctx, (void **)&res_d, sizeof(BatchResult) * (size_t)k)) != MF_OK ||
+        (st = dalloc(ctx, (void **)&q_d, sizeof(BatchQueue) * 4)) != MF_OK ||
+        (st = dalloc(ctx, (void **)&order_d, 4 * (size_t)k)) != MF_OK ||
+        (st = dalloc(ctx, (void **)&stage64, stage_bytes)) != MF_OK) {
+        release();
+        return st;
+    }
+    hipStream_t s0 = ctx->stream;
+    auto dev_err = [&](hipError_t e, const char *what) {
+        release();
+        return fail(ctx, MF_EDEVICE, "%s failed: %s", what, hipGetErrorString(e));
+    };
+    hipError_t he = hipMemsetAsync(ctls, 0, ctl_bytes, s0);
+    if (he != hipSuccess) return dev_err(he, "hipMemsetAsync");
+    // upload and validate every instance (residency step)
+    const int maxg = ctx->num_cus * 8;
+    std::vector<BatchItem> items((size_t)k);
+    for (int i = 0; i < k; i++) {
+        if (!ok[i]) continue;
+        const mf_graph &gh = graphs[i];
+        const InstLayout &L = lay[i];
+        const size_t S = (size_t)gh.slots, N = (size_t)gh.n;
+        GraphView gv;
+        gv.n = gh.n;
+        gv.s = gh.s;
+        gv.t = gh.t;
+        gv.slots = (int32_t)gh.slots;
+        gv.off = (int32_t *)(arena + L.off);
+        gv.head = (int32_t *)(arena + L.head);
+        gv.rev = (int32_t *)(arena + L.rev);
+        gv.cap = (int32_t *)(arena + L.cap);
+        int64_t *off64 = stage64, *rev64 = stage64 + (N + 1);
+        he = hipMemcpyAsync(off64, gh.offsets, 8 * (N + 1), hipMemcpyHostToDevice, s0);
+        if (he == hipSuccess && S) he = hipMemcpyAsync(rev64, gh.rev, 8 * S, hipMemcpyHostToDevice, s0);
+        if (he == hipSuccess && S) he = hipMemcpyAsync((void *)gv.head, gh.head, 4 * S, hipMemcpyHostToDevice, s0);
+        if (he == hipSuccess && S) he = hipMemcpyAsync((void *)gv.cap, gh.cap, 4 * S, hipMemcpyHostToDevice, s0);
+        if (he != hipSuccess) return dev_err(he, "batch upload");
+        Ctl *c0 = ctls + 5 * (size_t)i;
+        launch_narrow(off64, rev64, (int32_t *)gv.off, (int32_t *)gv.rev, gh.n, gh.slots, c0,
+                      grid_for(std::max<int64_t>(S, N + 1), 256, maxg), s0);
+        // k_validate relies on valid offsets; it only reads segments inside [0, slots) because k_narrow
+        // clamps bad offsets to 0, so run it and report either error.
+        launch_validate(gv, c0, grid_for(S, 256, maxg), s0);
+        BatchItem &it = items[i];
+        it.g = gv;
+        StateView sv;
+        memset(&sv, 0, sizeof sv);
+        sv.res = (int32_t *)(arena + L.res);
+        sv.delta = (int32_t *)(arena + L.delta);
+        sv.C = (int32_t *)(arena + L.C);
+        sv.d = (int32_t *)(arena + L.d);
+        sv.dn = (int32_t *)(arena + L.dn);
+        sv.owner = (int32_t *)(arena + L.owner);
+        sv.A = (int32_t *)(arena + L.A);
+        sv.A2 = (int32_t *)(arena + L.A2);
+        sv.Q = (int32_t *)(arena + L.Q);
+        sv.Q2 = (int32_t *)(arena + L.Q2);
+        sv.H = (int32_t *)(arena + L.H);
+        sv.e = (int64_t *)(arena + L.e);
+        sv.act = arena + L.act;
+        sv.touched = arena + L.touched;
+        it.st = sv;
+        it.ctl = c0;
+        it.flow = L.flow ? (int32_t *)(arena + L.flow) : nullptr;
+        it.side = arena + L.side;
+        const mf_options &oi = o[i];
+        it.G = batch_lanes(oi.lanes_per_vertex, gh.n, gh.slots);
+        PhaseParams &P = it.p;
+        memset(&P, 0, sizeof P);
+        P.freq_num = oi.gr_freq_num;
+        P.freq_den = oi.gr_freq_den;
+        P.alpha = oi.gr_alpha;
+        P.beta = oi.gr_beta;
+        P.round_charge = oi.gr_round_charge;
+        P.max_rounds = oi.max_rounds;
+        P.dense_threshold = oi.dense_threshold > 0 ? oi.dense_threshold : std::max<int64_t>(512, gh.n / 16);
+        P.bu_factor = 8;
+        P.hubdeg = 64 * it.G;
+        P.limit_ticks = 0;
+        it.preflow_only = (oi.flags & MF_PREFLOW_ONLY) ? 1 : 0;
+        results[i].lanes_per_vertex = it.G;
+    }
+    // validation results
+    std::vector<Ctl> hc(5 * (size_t)k);
+    he = hipMemcpyAsync(hc.data(), ctls, ctl_bytes, hipMemcpyDeviceToHost, s0);
+    if (he == hipSuccess) he = hipStreamSynchronize(s0);
+    if (he != hipSuccess) return dev_err(he, "validation read-back");
+    std::vector<std::vector<int32_t>> bucket(4);
+    for (int i = 0; i < k; i++) {
+        if (!ok[i]) continue;
+        if (hc[5 * (size_t)i].err) {
+            ok[i] = 0;
+            results[i].status = MF_EINVAL;
+            continue;
+        }
+        const int G = items[i].G;
+        bucket[G == 4 ? 0 : G == 8 ? 1 : G == 16 ? 2 : 3].push_back(i);
+    }
+    std::vector<int32_t> order;
+    int boff[4], bcnt[4];
+    for (int b = 0; b < 4; b++) {
+        boff[b] = (int)order.size();
+        bcnt[b] = (int)bucket[b].size();
+        order.insert(order.end(), bucket[b].begin(), bucket[b].end());
+    }
+    he = hipMemcpyAsync(items_d, items.data(), sizeof(BatchItem) * (size_t)k, hipMemcpyHostToDevice, s0);
+    if (he == hipSuccess && !order.empty())
+        he = hipMemcpyAsync(order_d, order.data(), 4 * order.size(), hipMemcpyHostToDevice, s0);
+    if (he == hipSuccess) he = hipMemsetAsync(res_d, 0, sizeof(BatchResult) * (size_t)k, s0);
+    if (he == hipSuccess) he = hipStreamSynchronize(s0);
+    if (he != hipSuccess) return dev_err(he, "batch descriptors");
+    // one graph: fork to one stream per lane-count group, one persistent kernel each, join
+    if ((st = ensure_batch_streams(ctx)) != MF_OK) {
+        release();
+        return st;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    he = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) return dev_err(he, "hipStreamBeginCapture");
+    (void)hipEventRecord(ctx->bev[4], s0);
+    for (int b = 0; b < 4; b++) {
+        if (!bcnt[b]) continue;
+        const int G = 4 << b;
+        hipStream_t sb = ctx->bstream[b];
+        (void)hipStreamWaitEvent(sb, ctx->bev[4], 0);
+        launch_queue_init(q_d + b, bcnt[b], sb);
+        int per_cu = batch_blocks_per_cu(G);
+        if (per_cu <= 0) per_cu = 1;
+        const int grid = std::max(1, std::min(bcnt[b], per_cu * ctx->num_cus));
+        (void)launch_batch(G, grid, items_d, order_d + boff[b], res_d, q_d + b, sb);
+        (void)hipEventRecord(ctx->bev[b], sb);
+        (void)hipStreamWaitEvent(s0, ctx->bev[b], 0);
+    }
+    he = hipStreamEndCapture(s0, &graph);
+    if (he != hipSuccess) return dev_err(he, "hipStreamEndCapture");
+    he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return dev_err(he, "hipGraphInstantiate");
+    }
+    (void)hipEventRecord(ctx->ev[0], s0);
+    he = hipGraphLaunch(exec, s0);
+    (void)hipEventRecord(ctx->ev[2], s0);
+    if (he == hipSuccess) he = hipStreamSynchronize(s0);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (he != hipSuccess) return dev_err(he, "batch launch");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]);
+    std::vector<BatchResult> hr((size_t)k);
+    he = hipMemcpy(hr.data(), res_d, sizeof(BatchResult) * (size_t)k, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return dev_err(he, "batch results");
+    int64_t t0 = INT64_MAX;
+    for (int i = 0; i < k; i++)
+        if (ok[i]) t0 = std::min(t0, hr[i].t_start);
+    for (int i = 0; i < k; i++) {
+        if (!ok[i]) continue;
+        const BatchResult &r = hr[i];
+        mf_result &R = results[i];
+        R.status = r.status == 0 ? MF_OK : r.status == 1 ? MF_ETIMEOUT : MF_EDEVICE;
+        R.value = r.value;
+        R.cut_capacity = r.cut;
+        R.rounds = r.rounds;
+        R.rounds2 = r.rounds2;
+        R.global_relabels = r.grs;
+        R.global_relabels2 = r.grs2;
+        R.bfs_levels = r.levels;
+        R.pushes = r.pushes;
+        R.relabels = r.relabels;
+        R.ms_start = 1e3 * (double)(r.t_start - t0) / (double)ctx->wall_hz;
+        R.ms_end = 1e3 * (double)(r.t_end - t0) / (double)ctx->wall_hz;
+        const size_t S = (size_t)graphs[i].slots, N = (size_t)graphs[i].n;
+        if (flows && flows[i] && S && R.status == MF_OK)
+            he = hipMemcpy(flows[i], items[i].flow, 4 * S, hipMemcpyDeviceToHost);
+        if (he == hipSuccess && sides && sides[i]) he = hipMemcpy(sides[i], items[i].side, N, hipMemcpyDeviceToHost);
+        if (he != hipSuccess) return dev_err(he, "batch output copy");
+    }
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->ms_total = ms;
+    }
+    release();
+    return MF_OK;
 }
