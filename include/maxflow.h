@@ -182,8 +182,10 @@ typedef struct {
     int64_t value, cut_capacity;
     int64_t rounds, rounds2, global_relabels, global_relabels2, bfs_levels;
     int64_t pushes, relabels;
-    double ms_start, ms_end;     /* device time of the instance's start and end, from the
-                                    first instance's start */
+    double ms_start, ms_end;     /* batch: device time of the instance's start and end, from the
+                                    first instance's start; server: 0 and the device time of
+                                    the solve */
+    double ms_latency;           /* server: time from mf_server_submit to the result being ready */
 } mf_result;
 
 /* Solves k graphs given in host memory.  opts is NULL (the defaults for all)
@@ -197,6 +199,52 @@ typedef struct {
 mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *graphs, const mf_options *opts,
                          int32_t *const *flows, uint8_t *const *sides, mf_result *results,
                          mf_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * Served form: requests of mixed size arrive over time; the server admits
+ * them by HBM budget in arrival order, keeps each graph and its residual state
+ * in device memory until it is solved, and runs admitted requests with
+ * continuous batching (a request joins the running persistent kernel of its
+ * lane count as soon as a workgroup is free).  Results are identical to
+ * mf_solve's for the same options.  All server calls are thread-safe.
+ */
+typedef struct {
+    size_t hbm_budget_bytes;   /* device memory for requests, allocated once (0 = 64 GiB) */
+    int32_t max_inflight;      /* requests admitted at once (0 or above 4096 = 4096) */
+    int32_t idle_ms;           /* a serve kernel leaves after this long without work (0 = 20) */
+    int32_t blocks_per_cu;     /* serve kernel workgroups per compute unit (0 = occupancy limit) */
+    int32_t reserved[5];
+} mf_server_config;
+
+typedef struct {
+    int64_t submitted, admitted, completed, canceled, rejected;
+    int64_t inflight, queued;
+    size_t bytes_in_use, peak_bytes;
+    int64_t kernel_launches;
+} mf_server_stats;
+
+typedef struct mf_server mf_server;
+
+mf_status mf_server_create(mf_context *ctx, const mf_server_config *cfg, mf_server **out);
+/* Joins the worker, waits for the device and frees everything; results not
+ * yet polled are discarded. */
+void mf_server_destroy(mf_server *srv);
+/* Copies the graph (host pointers) and returns a ticket at once.  A request
+ * whose graph breaks the format gets MF_EINVAL, one larger than the whole
+ * budget MF_ENOMEM, both in its result. */
+mf_status mf_server_submit(mf_server *srv, const mf_graph *host_g, const mf_options *opt, int want_flow,
+                           uint64_t *ticket);
+/* MF_EAGAIN while the request is pending; otherwise fills *out (status of the
+ * request in out->status), copies flow (int32[slots]) and sink_side (uint8[n])
+ * if not NULL, and forgets the ticket (MF_ENOTFOUND afterwards). */
+mf_status mf_server_poll(mf_server *srv, uint64_t ticket, mf_result *out, int32_t *flow, uint8_t *sink_side);
+/* As mf_server_poll but waits up to timeout_ms (negative = no limit). */
+mf_status mf_server_wait(mf_server *srv, uint64_t ticket, int64_t timeout_ms, mf_result *out, int32_t *flow,
+                         uint8_t *sink_side);
+/* A request not yet admitted completes with MF_ECANCELED at once; an admitted
+ * one completes with MF_ECANCELED when its solve ends. */
+mf_status mf_server_cancel(mf_server *srv, uint64_t ticket);
+mf_status mf_server_get_stats(mf_server *srv, mf_server_stats *out);
 
 #ifdef __cplusplus
 }

@@ -62,7 +62,20 @@ class mf_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("lanes_per_vertex", ctypes.c_int32)] + [
         (k, ctypes.c_int64) for k in ("value", "cut_capacity", "rounds", "rounds2", "global_relabels",
                                       "global_relabels2", "bfs_levels", "pushes", "relabels")] + [
-        ("ms_start", ctypes.c_double), ("ms_end", ctypes.c_double)]
+        ("ms_start", ctypes.c_double), ("ms_end", ctypes.c_double), ("ms_latency", ctypes.c_double)]
+
+
+class mf_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("idle_ms", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class mf_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "completed", "canceled",
+                                              "rejected", "inflight", "queued")] + [
+        ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+        ("kernel_launches", ctypes.c_int64)]
 
 
 _LIB = None
@@ -82,6 +95,13 @@ SIGNATURES = [
     ("mf_solve", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve_device", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("mf_batch_solve", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
+    ("mf_server_create", ctypes.c_int, [_P, _P, _P]),
+    ("mf_server_destroy", None, [_P]),
+    ("mf_server_submit", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    ("mf_server_poll", ctypes.c_int, [_P, ctypes.c_uint64, _P, _P, _P]),
+    ("mf_server_wait", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int64, _P, _P, _P]),
+    ("mf_server_cancel", ctypes.c_int, [_P, ctypes.c_uint64]),
+    ("mf_server_get_stats", ctypes.c_int, [_P, _P]),
 ]
 
 
@@ -286,3 +306,72 @@ class DeviceGraph:
         out = _stats_dict(stats)
         out.update(status=st, value=int(val.value))
         return out
+
+
+class Server:
+    """An mf_server: admission by HBM budget, continuous batching, latency per request."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_inflight: int = 0, idle_ms: int = 0,
+                 blocks_per_cu: int = 0):
+        cfg = mf_server_config(int(hbm_budget_bytes), int(max_inflight), int(idle_ms), int(blocks_per_cu))
+        h = ctypes.c_void_p()
+        ctx._check(lib().mf_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.ctx, self.h = ctx, h
+        self._shapes = {}
+
+    def close(self):
+        if self.h:
+            lib().mf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, g, opt: mf_options | None = None, want_flow: bool = True) -> int:
+        hg = _HostGraph(g)
+        t = ctypes.c_uint64()
+        st = lib().mf_server_submit(self.h, ctypes.byref(hg.st), None if opt is None else ctypes.byref(opt),
+                                    int(want_flow), ctypes.byref(t))
+        if st != MF_OK:
+            raise MaxflowError(st, "submit failed")
+        self._shapes[t.value] = (g.n, hg.head.shape[0], want_flow)
+        return t.value
+
+    def _collect(self, fn, ticket, *extra):
+        if ticket not in self._shapes:
+            st = fn(self.h, ctypes.c_uint64(ticket), *extra, None, None, None)
+            raise MaxflowError(st, "unknown ticket")
+        n, S, wf = self._shapes[ticket]
+        res = mf_result()
+        flow = np.zeros(max(1, S), dtype=np.int32) if wf else None
+        side = np.zeros(n, dtype=np.uint8)
+        st = fn(self.h, ctypes.c_uint64(ticket), *extra, ctypes.byref(res),
+                None if flow is None else flow.ctypes.data, side.ctypes.data)
+        if st == MF_EAGAIN:
+            return None
+        if st != MF_OK:
+            raise MaxflowError(st, "poll failed")
+        del self._shapes[ticket]
+        d = _result_dict(res)
+        d["flow"] = None if flow is None else flow[:S]
+        d["sink_side"] = side
+        return d
+
+    def poll(self, ticket: int):
+        return self._collect(lib().mf_server_poll, ticket)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        return self._collect(lib().mf_server_wait, ticket, ctypes.c_int64(timeout_ms))
+
+    def cancel(self, ticket: int):
+        st = lib().mf_server_cancel(self.h, ctypes.c_uint64(ticket))
+        if st != MF_OK:
+            raise MaxflowError(st, "cancel failed")
+
+    def stats(self) -> dict:
+        s = mf_server_stats()
+        lib().mf_server_get_stats(self.h, ctypes.byref(s))
+        return {k: getattr(s, k) for k, _ in mf_server_stats._fields_}

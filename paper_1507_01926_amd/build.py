@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/kernels.hip", "csrc/persistent.hip", "csrc/solver.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/persistent.hip", "csrc/solver.hip", "csrc/server.hip"]
 TARGET = os.path.join(HERE, "libmaxflow.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

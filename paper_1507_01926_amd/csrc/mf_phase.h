@@ -32,6 +32,8 @@ struct BatchItem {
     PhaseParams p;         // schedule; sink / other are set per phase
     int32_t G;             // lanes per vertex: 4, 8, 16 or 32
     int32_t preflow_only;
+    const int64_t *off64;  // server: int64 offsets / reverse slots as received, narrowed and
+    const int64_t *rev64;  // checked by the block that takes the instance (null in a batch)
 };
 
 struct BatchResult {
@@ -44,6 +46,22 @@ struct BatchQueue {
     int32_t next;     // next position of `order` to hand out
     int32_t count;    // number of positions
 };
+
+// Served requests: queues in coherent host memory written by the host; `next`
+// lives in device memory and is advanced by compare-and-swap.
+constexpr int SERVE_CAP = 4096;          // queue slots (ring)
+
+struct ServeHostQueue {                  // pinned, coherent host memory
+    int32_t count;                       // items published (grows; slot = index % SERVE_CAP)
+    int32_t shutdown;
+    int32_t pad[14];
+    BatchItem items[SERVE_CAP];
+    BatchResult results[SERVE_CAP];
+    int32_t done[SERVE_CAP];             // index + 1 when results[slot] holds that index's result
+};
+
+hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, hipStream_t s);
+int serve_blocks_per_cu(int G);
 
 hipError_t launch_phase(int G, int grid, GraphView g, StateView st, PhaseParams P, Ctl *ring, Ctl *gc,
                         GridBar *bar, hipStream_t s);

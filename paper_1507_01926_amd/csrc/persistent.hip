@@ -384,6 +384,56 @@ __device__ void zero_ctls(Ctl *c, int k)
     for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
 }
 
+// Residency step done by the block that takes a served instance: narrow the
+// int64 offsets and reverse slots to int32 and check the graph (the checks of
+// k_narrow and k_validate).  Returns true if the graph is valid.
+__device__ __forceinline__ bool block_prepare(const BatchItem &it)
+{
+    __shared__ int s_err;
+    const GraphView g = it.g;
+    const int n = g.n, S = g.slots;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    int err = 0;
+    int32_t *off = (int32_t *)g.off, *rev = (int32_t *)g.rev;
+    for (int i = threadIdx.x; i <= n; i += blockDim.x) {
+        const int64_t o = it.off64[i];
+        if (o < 0 || o > S) err |= 1;
+        if (i == 0 && o != 0) err |= 1;
+        if (i == n && o != S) err |= 1;
+        if (i > 0 && o < it.off64[i - 1]) err |= 1;
+        off[i] = (o < 0 || o > S) ? 0 : (int32_t)o;
+    }
+    for (int a = threadIdx.x; a < S; a += blockDim.x) {
+        const int64_t r = it.rev64[a];
+        const bool okr = r >= 0 && r < S;
+        if (!okr) err |= 2;
+        rev[a] = okr ? (int32_t)r : a;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int a = threadIdx.x; a < S; a += blockDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= a) lo = mid; else hi = mid - 1;
+        }
+        const int v = lo;
+        const int w = g.head[a];
+        if (w < 0 || w >= n) { err |= 4; continue; }
+        if (w == v) err |= 8;
+        const int b = rev[a];
+        if (rev[b] != a || g.head[b] != v) err |= 16;
+        const int64_t c = g.cap[a];
+        if (c < 0) err |= 32;
+        if (c + (int64_t)g.cap[b] > 2147483647LL) err |= 64;
+    }
+    if (err) atomicOr(&s_err, err);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    return s_err == 0;
+}
+
 template <int G>
 __device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *out, int32_t *sbuf,
                                             int32_t *scnt, int32_t *sbase)
@@ -539,6 +589,84 @@ __global__ void k_queue_init(BatchQueue *q, int count)
 void launch_queue_init(BatchQueue *q, int count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_queue_init, dim3(1), dim3(1), 0, s, q, count);
+}
+
+// Served requests: every block repeatedly claims the next published item of
+// its queue (compare-and-swap on `next`, so an item is claimed only once it is
+// published), solves it and writes the result and a done mark to host memory.
+// A block leaves when the host asks for shutdown or when no item has arrived
+// for idle_ticks, so every wave exits.
+template <int G>
+__global__ __launch_bounds__(256) void k_serve(ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks)
+{
+    __shared__ int32_t sbuf[STAGE_CAP];
+    __shared__ int32_t scnt, sbase;
+    __shared__ int s_i;
+    __shared__ BatchItem s_item;
+    __shared__ BatchResult s_res;
+    while (true) {
+        if (threadIdx.x == 0) {
+            int claimed = -1;
+            const uint64_t t0 = wall_clock64();
+            while (true) {
+                const int c = __hip_atomic_load(&hq->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                int nx = __hip_atomic_load(next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (nx < c) {
+                    if (__hip_atomic_compare_exchange_strong(next, &nx, nx + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        claimed = nx;
+                        break;
+                    }
+                    continue;
+                }
+                if (__hip_atomic_load(&hq->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                if (wall_clock64() - t0 > idle_ticks) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+            s_i = claimed;
+            if (claimed >= 0) {
+                s_item = hq->items[claimed % SERVE_CAP];
+                s_res = BatchResult{};
+                s_res.t_start = wall_clock64();
+            }
+        }
+        __syncthreads();
+        const int i = s_i;
+        if (i < 0) break;
+        const BatchItem it = s_item;
+        if (block_prepare(it)) {
+            solve_block<G>(it, &s_res, sbuf, &scnt, &sbase);
+        } else if (threadIdx.x == 0) {
+            s_res.status = 3;    // invalid graph
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_res.t_end = wall_clock64();
+            hq->results[i % SERVE_CAP] = s_res;
+            __hip_atomic_store(&hq->done[i % SERVE_CAP], i + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, hipStream_t s)
+{
+    switch (G) {
+    case 4: hipLaunchKernelGGL(k_serve<4>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
+    case 8: hipLaunchKernelGGL(k_serve<8>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
+    case 16: hipLaunchKernelGGL(k_serve<16>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
+    default: hipLaunchKernelGGL(k_serve<32>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
+    }
+    return hipGetLastError();
+}
+
+int serve_blocks_per_cu(int G)
+{
+    int nb = 0;
+    const void *f = G == 4 ? (const void *)k_serve<4> : G == 8 ? (const void *)k_serve<8>
+                  : G == 16 ? (const void *)k_serve<16> : (const void *)k_serve<32>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess) return 0;
+    return nb;
 }
 
 int batch_blocks_per_cu(int G)

@@ -26,6 +26,7 @@
 #include "../../include/maxflow.h"
 #include "mf_device.h"
 #include "mf_phase.h"
+#include "mf_host.h"
 
 namespace mf {
 void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid,
@@ -58,109 +59,7 @@ void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s);
 
 using namespace mf;
 
-static thread_local std::string g_global_err;
-
-struct mf_dgraph {
-    int32_t n = 0, s = 0, t = 0;
-    int64_t slots = 0;
-    int32_t *off = nullptr, *head = nullptr, *rev = nullptr, *cap = nullptr;
-    size_t bytes = 0;
-    GraphView view() const
-    {
-        GraphView g;
-        g.n = n;
-        g.s = s;
-        g.t = t;
-        g.slots = (int32_t)slots;
-        g.off = off;
-        g.head = head;
-        g.rev = rev;
-        g.cap = cap;
-        return g;
-    }
-};
-
-struct Workspace {
-    int64_t n_cap = 0, s_cap = 0;
-    int32_t *res = nullptr, *delta = nullptr, *d = nullptr, *dn = nullptr, *owner = nullptr;
-    int64_t *e = nullptr;
-    uint8_t *act = nullptr, *side = nullptr, *touched = nullptr;
-    int32_t *A = nullptr, *A2 = nullptr, *C = nullptr, *Q = nullptr, *Q2 = nullptr, *H = nullptr;
-    size_t bytes = 0;
-};
-
-struct mf_context {
-    int device = 0;
-    size_t budget = 0;     // 0 = unbounded
-    size_t used = 0;       // bytes held (graphs + workspace)
-    hipStream_t stream = nullptr;
-    Ctl *ctl = nullptr;        // device: [0] main, [1..3] round ring, [4] global relabel (persistent)
-    Ctl *ctl_host = nullptr;   // pinned host mirror of all five
-    GridBar *bar = nullptr;    // device: persistent-kernel barrier
-    uint64_t wall_hz = 100000000ull;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t pev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // profiling
-    hipStream_t bstream[4] = {nullptr, nullptr, nullptr, nullptr};                 // batch groups
-    hipEvent_t bev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    Workspace ws;
-    int num_cus = 256;
-    std::string err;
-};
-
-// ---------------------------------------------------------------------------
-// Error helpers
-
-static mf_status fail(mf_context *ctx, mf_status st, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (ctx)
-        ctx->err = buf;
-    else
-        g_global_err = buf;
-    return st;
-}
-
-#define HIPCHK(ctx, expr)                                                                     \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail((ctx), MF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
-
-static int grid_for(int64_t items, int per_block, int max_grid)
-{
-    int64_t g = (items + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > max_grid) g = max_grid;
-    return (int)g;
-}
-
-static mf_status dalloc(mf_context *ctx, void **p, size_t bytes)
-{
-    if (bytes == 0) bytes = 4;
-    if (ctx->budget && ctx->used + bytes > ctx->budget)
-        return fail(ctx, MF_ENOMEM, "HBM budget exceeded: %zu held + %zu requested > %zu", ctx->used,
-                    bytes, ctx->budget);
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return fail(ctx, MF_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    }
-    ctx->used += bytes;
-    return MF_OK;
-}
-
-static void dfree(mf_context *ctx, void *p, size_t bytes)
-{
-    if (!p) return;
-    (void)hipFree(p);
-    if (bytes == 0) bytes = 4;
-    ctx->used -= std::min(ctx->used, bytes);
-}
+thread_local std::string g_global_err;
 
 // ---------------------------------------------------------------------------
 // Public helpers
@@ -883,63 +782,6 @@ extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_
 // ---------------------------------------------------------------------------
 // Batched solver (host side)
 
-namespace {
-
-struct InstLayout {
-    size_t off, head, rev, cap, res, delta, C, d, dn, owner, A, A2, Q, Q2, H, e, act, touched, side, flow;
-    size_t end;
-};
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-InstLayout layout_for(size_t base, int64_t n, int64_t S, bool want_flow)
-{
-    InstLayout L;
-    size_t p = base;
-    auto take = [&](size_t bytes) {
-        size_t at = p;
-        p = align256(p + std::max<size_t>(bytes, 4));
-        return at;
-    };
-    L.off = take(4 * (n + 1));
-    L.head = take(4 * S);
-    L.rev = take(4 * S);
-    L.cap = take(4 * S);
-    L.res = take(4 * S);
-    L.delta = take(4 * S);
-    L.C = take(4 * (S + n));
-    L.d = take(4 * n);
-    L.dn = take(4 * n);
-    L.owner = take(4 * n);
-    L.A = take(4 * n);
-    L.A2 = take(4 * n);
-    L.Q = take(4 * n);
-    L.Q2 = take(4 * n);
-    L.H = take(4 * n);
-    L.e = take(8 * n);
-    L.act = take(n);
-    L.touched = take(n);
-    L.side = take(n);
-    L.flow = want_flow ? take(4 * S) : 0;
-    L.end = p;
-    return L;
-}
-
-int batch_lanes(int requested, int64_t n, int64_t S)
-{
-    int G = requested;
-    if (G <= 0) {
-        const double avg = n > 0 ? (double)S / (double)n : 1.0;
-        G = 4;
-        while (G < avg && G < 32) G <<= 1;
-    }
-    if (G <= 4) return 4;
-    if (G <= 8) return 8;
-    if (G <= 16) return 16;
-    return 32;
-}
-
-}  // namespace
 
 extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *graphs, const mf_options *opts,
                                     int32_t *const *flows, uint8_t *const *sides, mf_result *results,

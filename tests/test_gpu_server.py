@@ -1,0 +1,85 @@
+"""Served form: requests of mixed size submitted while others run; each
+result must be the same alone and in the mix (bit for bit, and equal to the
+oracle).  Needs a GPU."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_config, random_graph, stream_instance
+from tests._graphs import path_graph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1507_01926_amd as mf
+    c = mf.Context(0)
+    yield c
+    c.close()
+
+
+def test_server_mix_equals_alone_and_oracle(ctx):
+    import paper_1507_01926_amd as mf
+    srv = mf.Server(ctx, hbm_budget_bytes=2 << 30)
+    graphs = [stream_instance(i, n_hi=3e4) for i in range(30)]
+    graphs += [random_graph(5 + i, 20 + 3 * i, 900 + i) for i in range(20)]
+    graphs += [make_config("c2", 16), make_config("c3", 8)]
+    tickets = []
+    for i, g in enumerate(graphs):
+        tickets.append(srv.submit(g))
+        if i % 7 == 3:
+            time.sleep(0.002)            # arrivals spread over time
+    results = [srv.wait(t, 120000) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(graphs) and st["peak_bytes"] <= 2 << 30
+    for g, r in zip(graphs, results):
+        assert r is not None and r["status"] == 0
+        alone = ctx.solve(g)
+        assert r["value"] == alone["value"] and r["cut_capacity"] == alone["value"]
+        assert (r["flow"] == alone["flow"]).all() and (r["sink_side"] == alone["sink_side"]).all()
+        assert r["rounds"] == alone["rounds"] and r["rounds2"] == alone["rounds2"]
+        B = oracle.sync_maxflow(g)
+        assert r["value"] == B["value"] and (r["flow"].astype(np.int64) == B["flow"]).all()
+        assert r["ms_latency"] > 0
+
+
+def test_server_budget_admission_and_rejections(ctx):
+    import paper_1507_01926_amd as mf
+    budget = 24 << 20
+    srv = mf.Server(ctx, hbm_budget_bytes=budget, max_inflight=8)
+    small = [make_config("c2", 64) for _ in range(12)]
+    huge = make_config("c2", 4)                    # larger than the whole budget
+    bad = path_graph([3, 4]); bad.cap = bad.cap.copy(); bad.cap[0] = -1
+    tickets = [srv.submit(g) for g in small]
+    t_huge = srv.submit(huge)
+    t_bad = srv.submit(bad)
+    res = [srv.wait(t, 60000) for t in tickets]
+    r_huge = srv.wait(t_huge, 60000)
+    r_bad = srv.wait(t_bad, 60000)
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    v = ctx.solve(small[0])["value"]
+    assert all(r["value"] == v for r in res)
+    assert r_huge["status"] == mf.MF_ENOMEM
+    assert r_bad["status"] == mf.MF_EINVAL
+    assert st["peak_bytes"] <= budget and st["rejected"] == 1
+
+
+def test_server_cancel_and_unknown_ticket(ctx):
+    import paper_1507_01926_amd as mf
+    srv = mf.Server(ctx, hbm_budget_bytes=256 << 20, max_inflight=1)
+    g = make_config("c3", 8)
+    t1 = srv.submit(g)
+    t2 = srv.submit(g)
+    srv.cancel(t2)                                 # still pending behind t1
+    r1 = srv.wait(t1, 60000)
+    r2 = srv.wait(t2, 60000)
+    assert r1["status"] == 0 and r2["status"] == mf.MF_ECANCELED
+    with pytest.raises(mf.MaxflowError):
+        srv.poll(t1)
+    srv.close()
