@@ -68,6 +68,94 @@ def cpu_baseline_leg(g, workload: str) -> dict:
             "seconds": dt, "oracle_value": A["value"]}
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
+
+
+def stream_leg(count: int, n_hi: float, seed_note: str) -> dict:
+    """Batched and served forms on a stream of `count` instances (family
+    uniform over the five generator rules, n log-uniform in [1e3, n_hi]),
+    with knobs from the autotuner, next to the plain solver run one request
+    at a time in arrival order."""
+    import numpy as np
+    import paper_1507_01926_amd as mf
+    from paper_1507_01926_amd.autotune import Autotuner
+    from workloads import stream_instance, stream_arrivals
+
+    t0 = time.perf_counter()
+    graphs = [stream_instance(i, n_hi=n_hi) for i in range(count)]
+    gen_s = time.perf_counter() - t0
+    arcs = sum(g.m_arcs for g in graphs)
+    ctx = mf.Context(0)
+    tuner = Autotuner(ctx, cache_path=None)
+    # tune on one sample per bucket (the knobs never change results)
+    seen, sample = set(), []
+    from paper_1507_01926_amd.autotune import bucket_of
+    for g in graphs:
+        b = bucket_of(g)
+        if b not in seen:
+            seen.add(b)
+            sample.append(g)
+    t0 = time.perf_counter()
+    tuner.tune(sample, mode="batch", reps=1, round_divisors=(0, 128, 32))
+    tune_s = time.perf_counter() - t0
+    opts = [tuner.options_for(g, "batch") for g in graphs]
+    # warm-up, then closed loop: every request present at t = 0
+    mf.batch_solve(ctx, graphs[: min(8, count)], opts=opts[: min(8, count)], want_flow=False)
+    t0 = time.perf_counter()
+    res, ms_dev = mf.batch_solve(ctx, graphs, opts=opts, want_flow=True, want_side=True)
+    closed_s = time.perf_counter() - t0
+    assert all(r["status"] == 0 for r in res)
+    batched = {"solves_per_s": count / closed_s, "arcs_per_s": arcs / closed_s,
+               "p50_ms": _pct([r["ms_end"] for r in res], 50), "p99_ms": _pct([r["ms_end"] for r in res], 99),
+               "wall_s": closed_s, "device_ms": ms_dev,
+               "note": "latency = completion time from the batch start (all requests at t=0)"}
+    # plain solver, one request at a time: service times
+    service = []
+    plain_vals = []
+    for g, o in zip(graphs, opts):
+        t1 = time.perf_counter()
+        r = ctx.solve(g, o)
+        service.append(time.perf_counter() - t1)
+        plain_vals.append(r["value"])
+    assert plain_vals == [r["value"] for r in res]
+    served = {}
+    for frac in (0.5, 0.8):
+        rate = frac * count / closed_s
+        arr = stream_arrivals(count, rate)
+        srv = mf.Server(ctx, hbm_budget_bytes=16 << 30)
+        tickets = []
+        t_start = time.perf_counter()
+        for i, g in enumerate(graphs):
+            delay = arr[i] - (time.perf_counter() - t_start)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(g, opts[i]))
+        out = [srv.wait(t, 600000) for t in tickets]
+        span = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        assert [r["value"] for r in out] == plain_vals
+        lat = [r["ms_latency"] for r in out]
+        # the plain solver on the same arrival trace, one at a time (FIFO)
+        fin, plat = 0.0, []
+        for a, sv in zip(arr, service):
+            fin = max(fin, a) + sv
+            plat.append(1e3 * (fin - a))
+        served[f"poisson_{frac}x"] = {
+            "rate_per_s": rate, "solves_per_s": count / span, "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+            "peak_hbm_bytes": st["peak_bytes"], "kernel_launches": st["kernel_launches"],
+            "plain_one_at_a_time": {"solves_per_s": count / fin if fin else None,
+                                    "p50_ms": _pct(plat, 50), "p99_ms": _pct(plat, 99)}}
+    ctx.close()
+    return {"stream": f"{count} instances, n log-uniform in [1e3, {n_hi:.0e}], families uniform over "
+                      f"the five generator rules ({seed_note})",
+            "arcs_total": arcs, "generate_s": gen_s, "autotune_s": tune_s,
+            "autotuned_buckets": len(sample), "batched": batched, "served": served,
+            "plain_one_at_a_time_solves_per_s": count / sum(service)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +165,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paper-schedule", action="store_true",
                     help="use the paper's global-relabel rule without the per-round charge")
+    ap.add_argument("--stream", type=int, default=256,
+                    help="instances of the batched/served stream leg (0 = skip)")
+    ap.add_argument("--stream-nmax", type=float, default=1e5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X "
@@ -156,6 +247,9 @@ def main():
                   "alg_frac_whole_solve": alg_bytes_total / dt / 1e9 / HBM_PEAK_GBS},
     }
     ctx.close()
+    if args.stream > 0:
+        print(f"[bench] stream leg x{args.stream}", file=sys.stderr, flush=True)
+        line["stream"] = stream_leg(args.stream, args.stream_nmax, "seeded")
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline_leg(g, args.workload)

@@ -1,0 +1,139 @@
+"""Autotuner for the solver's schedule knobs.
+
+The knobs change how fast a solve runs, never its result (the rounds are a
+function of their start state, so value, flow and sink side are the same for
+every lane count and dense threshold; the global-relabel schedule changes the
+path but not the maximum-flow value, cut or sink side):
+
+  lanes_per_vertex   lanes that discharge one vertex (the vertices-per-wave
+                     split: 64 / lanes vertices per wavefront)
+  round_divisor      per-round work charge (12n+2m)/round_divisor added to the
+                     global-relabel counter (0 = the paper's rule only), i.e.
+                     the global-relabel frequency
+  dense_divisor      rounds with more than n/dense_divisor active vertices walk
+                     all vertices instead of a list (the degree/size
+                     threshold between the two layouts)
+
+Instances are bucketed by (floor(log2 n), round(log2 average degree),
+whether the maximum degree exceeds 64x the average).  For each bucket the
+tuner times every candidate on sample instances through the C ABI and keeps
+the fastest in a JSON cache.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import options
+
+LANES = (4, 8, 16, 32)
+ROUND_DIVISORS = (0, 512, 128, 32)
+DENSE_DIVISORS = (64, 512, 4096)
+
+
+def bucket_of(g) -> str:
+    n = int(g.n)
+    slots = int(g.head.shape[0])
+    avg = slots / max(1, n)
+    deg = np.diff(np.asarray(g.off))
+    hub = int(deg.max(initial=0)) > 64 * max(1.0, avg)
+    return f"n{int(math.log2(max(2, n)))}-d{int(round(math.log2(max(1.0, avg))))}-h{int(hub)}"
+
+
+def knobs_to_options(g, knobs: dict, **extra):
+    thr = 12 * int(g.n) + 2 * int(g.head.shape[0])
+    rd = int(knobs.get("round_divisor", 0))
+    dd = int(knobs.get("dense_divisor", 0))
+    return options(lanes_per_vertex=int(knobs.get("lanes_per_vertex", 0)),
+                   gr_round_charge=(thr // rd) if rd else 0,
+                   dense_threshold=max(1, int(g.n) // dd) if dd else 0, **extra)
+
+
+class Autotuner:
+    def __init__(self, ctx, cache_path: str | None = None):
+        self.ctx = ctx
+        self.cache_path = cache_path
+        self.cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                self.cache = json.load(fh)
+
+    def save(self):
+        if self.cache_path:
+            tmp = self.cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(self.cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, self.cache_path)
+
+    def knobs_for(self, g, mode: str = "plain") -> dict:
+        key = f"{mode}:{bucket_of(g)}"
+        if key in self.cache:
+            return dict(self.cache[key]["knobs"])
+        avg = int(g.head.shape[0]) / max(1, int(g.n))
+        lanes = 4
+        while lanes < avg and lanes < 32:
+            lanes *= 2
+        return {"lanes_per_vertex": lanes, "round_divisor": 128, "dense_divisor": 512}
+
+    def options_for(self, g, mode: str = "plain", **extra):
+        return knobs_to_options(g, self.knobs_for(g, mode), **extra)
+
+    def _time_plain(self, dg, g, knobs, reps):
+        best = None
+        for _ in range(reps):
+            r = dg.solve(knobs_to_options(g, knobs))
+            best = r["ms_total"] if best is None else min(best, r["ms_total"])
+        return best
+
+    def _time_batch(self, graphs, knobs, reps):
+        from . import batch_solve
+        best = None
+        for _ in range(reps):
+            opts = [knobs_to_options(g, knobs) for g in graphs]
+            t0 = time.perf_counter()
+            batch_solve(self.ctx, graphs, opts=opts, want_flow=False, want_side=False)
+            dt = 1e3 * (time.perf_counter() - t0)
+            best = dt if best is None else min(best, dt)
+        return best
+
+    def tune(self, graphs, mode: str = "plain", reps: int = 2, lanes=LANES, round_divisors=ROUND_DIVISORS,
+             dense_divisors=DENSE_DIVISORS, verbose: bool = False) -> dict:
+        """Time every candidate on the given sample graphs (grouped by bucket)
+        and record the fastest per bucket.  Returns {bucket key: entry}."""
+        groups = {}
+        for g in graphs:
+            groups.setdefault(f"{mode}:{bucket_of(g)}", []).append(g)
+        out = {}
+        for key, gs in groups.items():
+            if mode == "batch":
+                cands = [dict(lanes_per_vertex=l, round_divisor=r, dense_divisor=512)
+                         for l, r in itertools.product(lanes, round_divisors)]
+            else:
+                cands = [dict(lanes_per_vertex=l, round_divisor=r, dense_divisor=d)
+                         for l, r, d in itertools.product(lanes, round_divisors, dense_divisors)]
+            timings = []
+            if mode == "plain":
+                dgs = [self.ctx.upload(g) for g in gs]
+                for c in cands:
+                    ms = sum(self._time_plain(dg, g, c, reps) for dg, g in zip(dgs, gs))
+                    timings.append((ms, c))
+                for dg in dgs:
+                    dg.free()
+            else:
+                for c in cands:
+                    timings.append((self._time_batch(gs, c, reps), c))
+            timings.sort(key=lambda x: x[0])
+            ms, best = timings[0]
+            entry = {"knobs": best, "ms": ms, "samples": len(gs),
+                     "candidates": [{"ms": t, "knobs": c} for t, c in timings]}
+            self.cache[key] = entry
+            out[key] = entry
+            if verbose:
+                print(f"[autotune] {key}: {best} {ms:.2f} ms over {len(gs)} sample(s)", flush=True)
+        self.save()
+        return out

@@ -87,3 +87,23 @@ int main(void) {
             ctypes.sizeof(mf.mf_result), ctypes.sizeof(mf.mf_server_config),
             ctypes.sizeof(mf.mf_server_stats), 4]
     assert sizes == mine
+
+
+def test_autotuner_buckets_and_defaults(tmp_path):
+    """Bucketing and the cache are host logic (no device needed)."""
+    from paper_1507_01926_amd import autotune
+    from workloads import make_config
+    g1 = make_config("c1")
+    g2 = make_config("c4b", 16)
+    assert autotune.bucket_of(g1) != autotune.bucket_of(g2)
+    assert autotune.bucket_of(g2).endswith("h1")          # R-MAT hubs
+    tuner = autotune.Autotuner(ctx=None, cache_path=str(tmp_path / "cache.json"))
+    k = tuner.knobs_for(g1)
+    assert k["lanes_per_vertex"] in autotune.LANES
+    tuner.cache["plain:" + autotune.bucket_of(g1)] = {"knobs": {"lanes_per_vertex": 16, "round_divisor": 32,
+                                                                "dense_divisor": 64}}
+    tuner.save()
+    again = autotune.Autotuner(ctx=None, cache_path=str(tmp_path / "cache.json"))
+    assert again.knobs_for(g1)["lanes_per_vertex"] == 16
+    o = again.options_for(g1)
+    assert o.lanes_per_vertex == 16 and o.gr_round_charge == (12 * g1.n + 2 * g1.slots) // 32
