@@ -38,7 +38,7 @@ WORKLOADS = {
 def tuned_schedule(g) -> dict:
     """Global-relabel schedule used by the benchmark: the paper's rule (freq
     1/2, alpha 6, beta 12) plus a per-round work charge of (12n+2m)/128, which
-    bounds the rounds between two global relabels (see the design notes)."""
+    bounds the rounds between two global relabels."""
     thr = 12 * g.n + 2 * g.slots
     return dict(gr_round_charge=max(1, thr // 128))
 
@@ -171,7 +171,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X "
-              "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+              "(no sharding across GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

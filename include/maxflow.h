@@ -109,8 +109,9 @@ typedef struct {
     double ms_preflow;   /* device time of phase 1 (init to maximum preflow) */
     double ms_total;     /* device time of the whole solve, outputs included */
     /* filled with MF_PROFILE (both phases): summed kernel durations, launch
-     * counts and algorithmic bytes (the bytes the method must move, by the
-     * per-unit model of the design notes) */
+     * counts and algorithmic bytes (the bytes the method must move: per
+     * discharged vertex, slot scanned, push, merged vertex and slot, and
+     * global-relabel slot and vertex) */
     double ms_discharge, ms_merge, ms_global_relabel;
     int64_t discharge_launches, merge_launches, global_relabel_launches;
     int64_t discharge_bytes, merge_bytes, global_relabel_bytes;
@@ -183,8 +184,9 @@ typedef struct {
     int64_t rounds, rounds2, global_relabels, global_relabels2, bfs_levels;
     int64_t pushes, relabels;
     double ms_start, ms_end;     /* batch: device time of the instance's start and end, from the
-                                    first instance's start; server: 0 and the device time of
-                                    the solve */
+                                    first instance's start; server: device time spent pulling
+                                    and checking the graph, and device time of the whole
+                                    request (pull, checks, solve, results sent back) */
     double ms_latency;           /* server: time from mf_server_submit to the result being ready */
 } mf_result;
 
@@ -204,8 +206,9 @@ mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *graphs, con
  * Served form: requests of mixed size arrive over time; the server admits
  * them by HBM budget in arrival order, keeps each graph and its residual state
  * in device memory until it is solved, and runs admitted requests with
- * continuous batching (a request joins the running persistent kernel of its
- * lane count as soon as a workgroup is free).  Results are identical to
+ * continuous batching (a request joins the running persistent kernel as soon
+ * as a workgroup is free; that workgroup pulls the graph from pinned host
+ * memory and sends the results back itself).  Results are identical to
  * mf_solve's for the same options.  All server calls are thread-safe.
  */
 typedef struct {
@@ -213,7 +216,10 @@ typedef struct {
     int32_t max_inflight;      /* requests admitted at once (0 or above 4096 = 4096) */
     int32_t idle_ms;           /* a serve kernel leaves after this long without work (0 = 20) */
     int32_t blocks_per_cu;     /* serve kernel workgroups per compute unit (0 = occupancy limit) */
-    int32_t reserved[5];
+    int32_t host_staging_mib;  /* pinned host memory through which graphs and results pass, in MiB
+                                  (0 = the budget, at most 1 GiB); a request needs 8(n+1) + 16 slots
+                                  bytes of it, each part rounded up to 256, while it is in flight */
+    int32_t reserved[4];
 } mf_server_config;
 
 typedef struct {
@@ -231,7 +237,7 @@ mf_status mf_server_create(mf_context *ctx, const mf_server_config *cfg, mf_serv
 void mf_server_destroy(mf_server *srv);
 /* Copies the graph (host pointers) and returns a ticket at once.  A request
  * whose graph breaks the format gets MF_EINVAL, one larger than the whole
- * budget MF_ENOMEM, both in its result. */
+ * HBM budget or the whole host staging arena MF_ENOMEM, both in its result. */
 mf_status mf_server_submit(mf_server *srv, const mf_graph *host_g, const mf_options *opt, int want_flow,
                            uint64_t *ticket);
 /* MF_EAGAIN while the request is pending; otherwise fills *out (status of the

@@ -85,8 +85,9 @@ typedef struct {
     /* added to W once per round (0 in the paper's rule) */
     int64_t round_charge;
     /* 1: end as the listing does, by filtering the old working set after a
-     * global relabel and stopping when it is empty (can end early: see the
-     * design notes); 0: rebuild the working set at every global relabel and
+     * global relabel and stopping when it is empty (can end early, with
+     * excess stranded at vertices whose label passed a winner that pushed
+     * into them); 0: rebuild the working set at every global relabel and
      * stop only after one that finds no active vertex */
     int64_t literal_termination;
 } og_sched;

@@ -3,8 +3,7 @@
  * with its parallel global relabeling (Listing 2), executed one vertex at a
  * time in exact int64.  Test infrastructure only (see oracle.h).
  *
- * Readings of points the pseudocode leaves open (each one is listed with its
- * reason in the design notes):
+ * Readings of points the pseudocode leaves open:
  *  - initial working set: the distinct heads of saturated source arcs other
  *    than s and t; the first iteration always runs a global relabel, which
  *    filters it;

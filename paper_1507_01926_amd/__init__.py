@@ -68,7 +68,7 @@ class mf_result(ctypes.Structure):
 class mf_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
                 ("idle_ms", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("host_staging_mib", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class mf_server_stats(ctypes.Structure):
@@ -312,8 +312,9 @@ class Server:
     """An mf_server: admission by HBM budget, continuous batching, latency per request."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_inflight: int = 0, idle_ms: int = 0,
-                 blocks_per_cu: int = 0):
-        cfg = mf_server_config(int(hbm_budget_bytes), int(max_inflight), int(idle_ms), int(blocks_per_cu))
+                 blocks_per_cu: int = 0, host_staging_mib: int = 0):
+        cfg = mf_server_config(int(hbm_budget_bytes), int(max_inflight), int(idle_ms), int(blocks_per_cu),
+                               int(host_staging_mib))
         h = ctypes.c_void_p()
         ctx._check(lib().mf_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
         self.ctx, self.h = ctx, h

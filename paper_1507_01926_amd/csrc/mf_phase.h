@@ -32,13 +32,23 @@ struct BatchItem {
     PhaseParams p;         // schedule; sink / other are set per phase
     int32_t G;             // lanes per vertex: 4, 8, 16 or 32
     int32_t preflow_only;
-    const int64_t *off64;  // server: int64 offsets / reverse slots as received, narrowed and
-    const int64_t *rev64;  // checked by the block that takes the instance (null in a batch)
+    // Served requests only (null in a batch): the graph as received, in
+    // pinned coherent host memory (int64 offsets and reverse slots, int32
+    // heads and capacities, each 256-byte aligned), which the block that
+    // takes the request pulls into device memory and checks; and host
+    // buffers that receive the sink side and the flow at the end.
+    const int64_t *off64;
+    const int64_t *rev64;
+    const int32_t *head_h;
+    const int32_t *cap_h;
+    uint8_t *side_h;
+    int32_t *flow_h;
 };
 
 struct BatchResult {
     int64_t value, cut, rounds, rounds2, grs, grs2, levels, pushes, relabels;
     int64_t t_start, t_end;          // wall-clock ticks
+    int64_t t_solve;                 // served: when the pull and checks ended
     int32_t status, block;
 };
 
@@ -60,7 +70,12 @@ struct ServeHostQueue {                  // pinned, coherent host memory
     int32_t done[SERVE_CAP];             // index + 1 when results[slot] holds that index's result
 };
 
-hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, hipStream_t s);
+// next: device memory, [0] next index to claim, [4..7] mirror of the host
+// queue (published count, shutdown, number of requests finished, epoch of the
+// launch whose watcher has left); zeroed once when the queue is created and
+// kept across launches.  epoch: 1, 2, ... per launch.
+hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, int epoch,
+                        hipStream_t s);
 int serve_blocks_per_cu(int G);
 
 hipError_t launch_phase(int G, int grid, GraphView g, StateView st, PhaseParams P, Ctl *ring, Ctl *gc,

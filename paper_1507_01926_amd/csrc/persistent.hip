@@ -384,54 +384,115 @@ __device__ void zero_ctls(Ctl *c, int k)
     for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
 }
 
-// Residency step done by the block that takes a served instance: narrow the
-// int64 offsets and reverse slots to int32 and check the graph (the checks of
-// k_narrow and k_validate).  Returns true if the graph is valid.
+// Copies `bytes` between host and device memory by one block; both ends
+// 16-byte aligned.  Four 16-byte accesses are in flight per lane, since a
+// load from host memory waits for a PCIe round trip.
+__device__ __forceinline__ void block_copy(void *__restrict__ dst, const void *__restrict__ src, int64_t bytes)
+{
+    const int64_t nv = bytes >> 4;
+    const int4 *__restrict__ s4 = (const int4 *)src;
+    int4 *__restrict__ d4 = (int4 *)dst;
+    const int B = blockDim.x;
+    int64_t i = threadIdx.x;
+    for (; i + 3 * B < nv; i += 4 * B) {
+        const int4 x0 = s4[i], x1 = s4[i + B], x2 = s4[i + 2 * B], x3 = s4[i + 3 * B];
+        d4[i] = x0;
+        d4[i + B] = x1;
+        d4[i + 2 * B] = x2;
+        d4[i + 3 * B] = x3;
+    }
+    for (; i < nv; i += B) d4[i] = s4[i];
+    const uint8_t *s1 = (const uint8_t *)src;
+    uint8_t *d1 = (uint8_t *)dst;
+    for (int64_t j = 16 * nv + threadIdx.x; j < bytes; j += B) d1[j] = s1[j];
+}
+
+__device__ __forceinline__ int32_t narrow_one(int64_t x, int64_t j, int64_t hi, int32_t &err, int32_t bit,
+                                              bool self_fill)
+{
+    const bool ok = x >= 0 && x <= hi;
+    if (!ok) err |= bit;
+    return ok ? (int32_t)x : (self_fill ? (int32_t)j : 0);
+}
+
+// Narrows `count` int64 values from host memory into int32 device memory,
+// flagging values outside [0, hi] (replaced by 0, or by their own index when
+// self_fill, so that later reads stay in bounds).  src 16-byte aligned.
+__device__ __forceinline__ void block_narrow(int32_t *__restrict__ dst, const int64_t *__restrict__ src,
+                                             int64_t count, int64_t hi, int32_t &err, int32_t bit, bool self_fill)
+{
+    const int64_t np = count >> 1;          // pairs
+    const int4 *__restrict__ s4 = (const int4 *)src;
+    const int B = blockDim.x;
+    auto put = [&](int64_t p, int4 q) {
+        const int64_t x0 = (int64_t)(uint32_t)q.x | ((int64_t)q.y << 32);
+        const int64_t x1 = (int64_t)(uint32_t)q.z | ((int64_t)q.w << 32);
+        dst[2 * p] = narrow_one(x0, 2 * p, hi, err, bit, self_fill);
+        dst[2 * p + 1] = narrow_one(x1, 2 * p + 1, hi, err, bit, self_fill);
+    };
+    int64_t p = threadIdx.x;
+    for (; p + 3 * B < np; p += 4 * B) {
+        const int4 q0 = s4[p], q1 = s4[p + B], q2 = s4[p + 2 * B], q3 = s4[p + 3 * B];
+        put(p, q0);
+        put(p + B, q1);
+        put(p + 2 * B, q2);
+        put(p + 3 * B, q3);
+    }
+    for (; p < np; p += B) put(p, s4[p]);
+    if ((count & 1) && threadIdx.x == 0) dst[count - 1] = narrow_one(src[count - 1], count - 1, hi, err, bit, self_fill);
+}
+
+// Residency step done by the block that takes a served request: pull the
+// graph from host memory, narrow the int64 offsets and reverse slots to
+// int32, and check it (the checks of k_narrow and k_validate; eight lanes
+// walk the slots of one vertex).  Returns true if the graph is valid.
 __device__ __forceinline__ bool block_prepare(const BatchItem &it)
 {
     __shared__ int s_err;
     const GraphView g = it.g;
     const int n = g.n, S = g.slots;
+    // the host wrote the request before publishing it; drop any cached copy
+    // of an earlier request that used the same host or device memory
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     if (threadIdx.x == 0) s_err = 0;
-    __syncthreads();
-    int err = 0;
+    int32_t err = 0;
     int32_t *off = (int32_t *)g.off, *rev = (int32_t *)g.rev;
-    for (int i = threadIdx.x; i <= n; i += blockDim.x) {
-        const int64_t o = it.off64[i];
-        if (o < 0 || o > S) err |= 1;
-        if (i == 0 && o != 0) err |= 1;
-        if (i == n && o != S) err |= 1;
-        if (i > 0 && o < it.off64[i - 1]) err |= 1;
-        off[i] = (o < 0 || o > S) ? 0 : (int32_t)o;
-    }
-    for (int a = threadIdx.x; a < S; a += blockDim.x) {
-        const int64_t r = it.rev64[a];
-        const bool okr = r >= 0 && r < S;
-        if (!okr) err |= 2;
-        rev[a] = okr ? (int32_t)r : a;
-    }
+    block_narrow(off, it.off64, (int64_t)n + 1, S, err, 1, false);
+    block_narrow(rev, it.rev64, S, (int64_t)S - 1, err, 2, true);
+    block_copy((void *)g.head, it.head_h, 4 * (int64_t)S);
+    block_copy((void *)g.cap, it.cap_h, 4 * (int64_t)S);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int a = threadIdx.x; a < S; a += blockDim.x) {
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= a) lo = mid; else hi = mid - 1;
+    if (threadIdx.x == 0 && (off[0] != 0 || off[n] != S)) err |= 1;
+    constexpr int L = 8;
+    const int team = threadIdx.x / L, gl = threadIdx.x % L, teams = blockDim.x / L;
+    for (int v = team; v < n; v += teams) {
+        const int a0 = off[v], a1 = off[v + 1];
+        if (a1 < a0) err |= 1;
+        for (int a = a0 + gl; a < a1; a += L) {
+            const int w = g.head[a];
+            if (w < 0 || w >= n) { err |= 4; continue; }
+            if (w == v) err |= 8;
+            const int b = rev[a];
+            if (rev[b] != a || g.head[b] != v) err |= 16;
+            const int64_t c = g.cap[a];
+            if (c < 0) err |= 32;
+            if (c + (int64_t)g.cap[b] > 2147483647LL) err |= 64;
         }
-        const int v = lo;
-        const int w = g.head[a];
-        if (w < 0 || w >= n) { err |= 4; continue; }
-        if (w == v) err |= 8;
-        const int b = rev[a];
-        if (rev[b] != a || g.head[b] != v) err |= 16;
-        const int64_t c = g.cap[a];
-        if (c < 0) err |= 32;
-        if (c + (int64_t)g.cap[b] > 2147483647LL) err |= 64;
     }
     if (err) atomicOr(&s_err, err);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     return s_err == 0;
+}
+
+// Sends the sink side and the flow of a finished served request to its host
+// buffers and makes them visible to the host before the block reports done.
+__device__ __forceinline__ void block_publish(const BatchItem &it)
+{
+    if (it.side_h && it.side) block_copy(it.side_h, it.side, it.g.n);
+    if (it.flow_h && it.flow) block_copy(it.flow_h, it.flow, 4 * (int64_t)it.g.slots);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
 }
 
 template <int G>
@@ -540,6 +601,7 @@ __device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *ou
     if (threadIdx.x == 0) {
         r.t_end = wall_clock64();
         r.t_start = out->t_start;
+        r.t_solve = out->t_solve;
         r.block = blockIdx.x;
         *out = r;
     }
@@ -591,25 +653,74 @@ void launch_queue_init(BatchQueue *q, int count, hipStream_t s)
     hipLaunchKernelGGL(k_queue_init, dim3(1), dim3(1), 0, s, q, count);
 }
 
-// Served requests: every block repeatedly claims the next published item of
-// its queue (compare-and-swap on `next`, so an item is claimed only once it is
-// published), solves it and writes the result and a done mark to host memory.
-// A block leaves when the host asks for shutdown or when no item has arrived
-// for idle_ticks, so every wave exits.
 template <int G>
-__global__ __launch_bounds__(256) void k_serve(ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks)
+__device__ __forceinline__ void solve_block_any(const BatchItem &it, BatchResult *out, int32_t *sbuf,
+                                                int32_t *scnt, int32_t *sbase)
+{
+    if constexpr (G > 0) {
+        solve_block<G>(it, out, sbuf, scnt, sbase);
+    } else {
+        switch (it.G) {
+        case 4: solve_block<4>(it, out, sbuf, scnt, sbase); break;
+        case 8: solve_block<8>(it, out, sbuf, scnt, sbase); break;
+        case 16: solve_block<16>(it, out, sbuf, scnt, sbase); break;
+        default: solve_block<32>(it, out, sbuf, scnt, sbase); break;
+        }
+    }
+}
+
+// Served requests.  Workgroup 0 watches the host-side queue: it copies the
+// published count and the shutdown flag into device memory (mirror[0],
+// mirror[1]) about once a microsecond, so the other workgroups, which take
+// the requests, poll device memory only.  A workgroup claims the next
+// published item by compare-and-swap on `next` (an item is claimed only once
+// it is published), solves it (G = 0: with the item's own lane count) and
+// writes the result and a done mark to host memory.  Every workgroup leaves
+// when the host asks for shutdown or when no request has arrived for
+// idle_ticks, so every wave exits.
+template <int G>
+__global__ __launch_bounds__(256) void k_serve(ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, int epoch)
 {
     __shared__ int32_t sbuf[STAGE_CAP];
     __shared__ int32_t scnt, sbase;
     __shared__ int s_i;
     __shared__ BatchItem s_item;
     __shared__ BatchResult s_res;
+    int32_t *mirror = next + 4;       // [0] published count, [1] shutdown
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            int last = __hip_atomic_load(&hq->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&mirror[0], last, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t t0 = wall_clock64();
+            while (true) {
+                const int c = __hip_atomic_load(&hq->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (c != last) {
+                    last = c;
+                    __hip_atomic_store(&mirror[0], c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    t0 = wall_clock64();
+                }
+                if (__hip_atomic_load(&hq->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                    __hip_atomic_store(&mirror[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                // keep watching while requests are still being solved
+                const int nx = __hip_atomic_load(next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int dn = __hip_atomic_load(&mirror[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (nx >= c && dn >= nx && wall_clock64() - t0 > idle_ticks) break;
+                __builtin_amdgcn_s_sleep(32);
+            }
+            __hip_atomic_store(&mirror[3], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
     while (true) {
         if (threadIdx.x == 0) {
             int claimed = -1;
-            const uint64_t t0 = wall_clock64();
+            uint64_t t0 = wall_clock64();
+            int seen = -1;
+            int backoff = 1;
             while (true) {
-                const int c = __hip_atomic_load(&hq->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                const int c = __hip_atomic_load(&mirror[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                 int nx = __hip_atomic_load(next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (nx < c) {
                     if (__hip_atomic_compare_exchange_strong(next, &nx, nx + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
@@ -619,12 +730,25 @@ __global__ __launch_bounds__(256) void k_serve(ServeHostQueue *hq, int32_t *next
                     }
                     continue;
                 }
-                if (__hip_atomic_load(&hq->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
-                if (wall_clock64() - t0 > idle_ticks) break;
-                __builtin_amdgcn_s_sleep(8);
+                if (c != seen) {
+                    seen = c;
+                    t0 = wall_clock64();
+                }
+                // leave when the watcher has left, on shutdown, or (a backstop
+                // in case the watcher is not running) after a long quiet spell
+                if (__hip_atomic_load(&mirror[3], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+                if (__hip_atomic_load(&mirror[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                if (wall_clock64() - t0 > 50 * idle_ticks) break;
+                // Idle workgroups back off exponentially (to about 50 us
+                // between polls): hundreds of them polling one cache line
+                // would keep its L2 channel busy and slow the solving
+                // workgroups' loads that map to it.
+                for (int k = 0; k < backoff; k++) __builtin_amdgcn_s_sleep(127);
+                backoff = backoff < 16 ? 2 * backoff : 16;
             }
             s_i = claimed;
             if (claimed >= 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");    // the item is host-written
                 s_item = hq->items[claimed % SERVE_CAP];
                 s_res = BatchResult{};
                 s_res.t_start = wall_clock64();
@@ -635,27 +759,33 @@ __global__ __launch_bounds__(256) void k_serve(ServeHostQueue *hq, int32_t *next
         if (i < 0) break;
         const BatchItem it = s_item;
         if (block_prepare(it)) {
-            solve_block<G>(it, &s_res, sbuf, &scnt, &sbase);
+            if (threadIdx.x == 0) s_res.t_solve = wall_clock64();
+            solve_block_any<G>(it, &s_res, sbuf, &scnt, &sbase);
         } else if (threadIdx.x == 0) {
             s_res.status = 3;    // invalid graph
         }
+        __syncthreads();
+        if (s_res.status == 0) block_publish(it);
         __syncthreads();
         if (threadIdx.x == 0) {
             s_res.t_end = wall_clock64();
             hq->results[i % SERVE_CAP] = s_res;
             __hip_atomic_store(&hq->done[i % SERVE_CAP], i + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_fetch_add(&mirror[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, hipStream_t s)
+hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, int epoch,
+                        hipStream_t s)
 {
     switch (G) {
-    case 4: hipLaunchKernelGGL(k_serve<4>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
-    case 8: hipLaunchKernelGGL(k_serve<8>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
-    case 16: hipLaunchKernelGGL(k_serve<16>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
-    default: hipLaunchKernelGGL(k_serve<32>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks); break;
+    case 0: hipLaunchKernelGGL(k_serve<0>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
+    case 4: hipLaunchKernelGGL(k_serve<4>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
+    case 8: hipLaunchKernelGGL(k_serve<8>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
+    case 16: hipLaunchKernelGGL(k_serve<16>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
+    default: hipLaunchKernelGGL(k_serve<32>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
     }
     return hipGetLastError();
 }
@@ -663,8 +793,9 @@ hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint
 int serve_blocks_per_cu(int G)
 {
     int nb = 0;
-    const void *f = G == 4 ? (const void *)k_serve<4> : G == 8 ? (const void *)k_serve<8>
-                  : G == 16 ? (const void *)k_serve<16> : (const void *)k_serve<32>;
+    const void *f = G == 0 ? (const void *)k_serve<0> : G == 4 ? (const void *)k_serve<4>
+                  : G == 8 ? (const void *)k_serve<8> : G == 16 ? (const void *)k_serve<16>
+                  : (const void *)k_serve<32>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess) return 0;
     return nb;
 }

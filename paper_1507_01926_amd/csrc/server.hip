@@ -5,17 +5,22 @@
 //    ticket at once.
 //  - A worker thread admits requests in arrival order while the device
 //    region (one allocation of the budget's size, carved by a best-fit
-//    allocator) and the in-flight limit allow, copies the graph to its
-//    slice by DMA and publishes it to the queue of its lane count, in
-//    coherent host memory.
-//  - One persistent kernel per lane count keeps taking published requests
-//    (one workgroup per request: residency checks, both phases, outputs)
-//    while it runs; a request that arrives while others are on the GPU joins
-//    the running kernel as soon as a workgroup is free.  A kernel that finds
+//    allocator), the pinned host staging arena and the in-flight limit
+//    allow, writes the graph into its staging slice and publishes the
+//    request to the queue in coherent host memory.
+//  - One persistent kernel, launched with every workgroup the device can
+//    hold, keeps taking published requests (one workgroup per request:
+//    pulling the graph from host memory into its device slice, residency
+//    checks, both phases, outputs sent back to the staging slice, with the
+//    request's own lane count) while it runs; a request that arrives while others are on the
+//    GPU joins the running kernel as soon as a workgroup is free.  A kernel that finds
 //    no work for idle_ms leaves; the worker starts it again when requests
 //    arrive.
-//  - Finished requests are copied back, their device slice is freed, and
-//    mf_server_poll / mf_server_wait return them.
+//  - Finished requests are read from their staging slice, their slices are
+//    freed, and mf_server_poll / mf_server_wait return them.
+// No runtime copy runs while the serve kernel runs: all transfers are done
+// by the kernel's own loads and stores over PCIe, so a kernel that keeps
+// every compute unit busy never waits for a copy queued behind it.
 // Graphs and residual state stay in device memory for the whole solve.
 #include <hip/hip_runtime.h>
 
@@ -85,7 +90,7 @@ class RegionAllocator {
     size_t size_ = 0, used_ = 0;
 };
 
-enum ReqState { PENDING, PUBLISHED, COMPLETE };
+enum ReqState { STAGING, PENDING, ADMITTING, PUBLISHED, COMPLETE };
 
 struct Request {
     uint64_t ticket = 0;
@@ -99,6 +104,8 @@ struct Request {
     int G = 4, queue = 0;
     int32_t index = -1;          // position in its queue
     size_t bytes = 0, region_off = 0;
+    size_t host_bytes = 0, host_off = 0;
+    bool staged = false;         // graph already in its host staging slice
     InstLayout lay;
     ReqState state = PENDING;
     Clock::time_point t_submit, t_done;
@@ -107,15 +114,29 @@ struct Request {
     std::vector<uint8_t> side;
 };
 
-// Slice of one request: the instance layout, then the int64 offsets and
-// reverse slots as received, then the five control blocks.
-size_t staging_rev(int64_t n) { return align256(8 * (size_t)(n + 1)); }
-size_t staging_ctl(int64_t n, int64_t S) { return staging_rev(n) + align256(8 * (size_t)std::max<int64_t>(S, 1)); }
-
+// Device slice of one request: the instance layout, then the five control
+// blocks.
 size_t request_bytes(int64_t n, int64_t S, bool want_flow)
 {
     InstLayout L = layout_for(0, n, S, want_flow);
-    return L.end + staging_ctl(n, S) + align256(5 * sizeof(Ctl));
+    return L.end + align256(5 * sizeof(Ctl));
+}
+
+// Host staging slice of one request: int64 offsets, int64 reverse slots,
+// int32 heads, int32 capacities as received.  The results reuse it once the
+// graph has been pulled: the sink side at the start, the flow at the second
+// part (both fit the parts they overwrite).
+struct HostLayout {
+    size_t rev, head, cap, end;
+};
+HostLayout host_layout(int64_t n, int64_t S)
+{
+    HostLayout h;
+    h.rev = align256(8 * (size_t)(n + 1));
+    h.head = h.rev + align256(8 * (size_t)S);
+    h.cap = h.head + align256(4 * (size_t)S);
+    h.end = h.cap + align256(4 * (size_t)S);
+    return h;
 }
 
 }  // namespace
@@ -125,11 +146,13 @@ struct mf_server {
     mf_server_config cfg;
     uint8_t *region = nullptr;
     RegionAllocator alloc;
+    uint8_t *harena = nullptr;       // pinned coherent host staging arena
+    size_t harena_bytes = 0;
+    RegionAllocator halloc;
     ServeHostQueue *hq[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *next_d = nullptr;       // [4] device counters
     int32_t published[4] = {0, 0, 0, 0};
     hipStream_t kstream[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipStream_t copy = nullptr;
     uint64_t idle_ticks = 0;
     int grid[4] = {0, 0, 0, 0};
 
@@ -142,11 +165,32 @@ struct mf_server {
     std::unordered_map<uint64_t, Request *> reqs;
     std::vector<Request *> inflight_list;
     std::vector<Request *> slot_owner[4];
+    int64_t unstaged = 0;            // pending requests whose graph waits in pageable memory
     mf_server_stats st;
+    size_t bytes_in_use = 0;
     std::string err;
 };
 
 static void server_loop(mf_server *sv);
+
+// Gives back what a request that will not be admitted holds on the host
+// side (called with the lock held).
+static void drop_staging(mf_server *sv, Request *r)
+{
+    if (r->staged) {
+        sv->halloc.release(r->host_off, r->host_bytes);
+        r->staged = false;
+    } else {
+        sv->unstaged--;
+    }
+    std::vector<int64_t>().swap(r->off);
+    std::vector<int64_t>().swap(r->rev);
+    std::vector<int32_t>().swap(r->head);
+    std::vector<int32_t>().swap(r->cap);
+}
+
+static void stage_graph(mf_server *sv, Request *r, const int64_t *off, const int64_t *rev, const int32_t *head,
+                        const int32_t *cap);
 
 extern "C" mf_status mf_server_create(mf_context *ctx, const mf_server_config *cfg, mf_server **out)
 {
@@ -179,15 +223,19 @@ extern "C" mf_status mf_server_create(mf_context *ctx, const mf_server_config *c
         memset(sv->hq[q], 0, sizeof(ServeHostQueue));
         if (hipStreamCreateWithFlags(&sv->kstream[q], hipStreamNonBlocking) != hipSuccess)
             return bail(MF_EDEVICE, "stream creation failed");
-        int per_cu = serve_blocks_per_cu(4 << q);
+        int per_cu = serve_blocks_per_cu(0);
         if (per_cu <= 0) per_cu = 1;
         if (sv->cfg.blocks_per_cu > 0) per_cu = std::min(per_cu, (int)sv->cfg.blocks_per_cu);
         sv->grid[q] = per_cu * ctx->num_cus;
     }
-    if (hipStreamCreateWithFlags(&sv->copy, hipStreamNonBlocking) != hipSuccess)
-        return bail(MF_EDEVICE, "stream creation failed");
-    if (hipMalloc((void **)&sv->next_d, 4 * sizeof(int32_t)) != hipSuccess ||
-        hipMemset(sv->next_d, 0, 4 * sizeof(int32_t)) != hipSuccess)
+    sv->harena_bytes = sv->cfg.host_staging_mib > 0 ? (size_t)sv->cfg.host_staging_mib << 20
+                                                    : std::min(sv->cfg.hbm_budget_bytes, (size_t)1 << 30);
+    sv->harena_bytes = align256(sv->harena_bytes);
+    if (hipHostMalloc((void **)&sv->harena, sv->harena_bytes, hipHostMallocCoherent) != hipSuccess)
+        return bail(MF_ENOMEM, "pinned staging allocation failed");
+    sv->halloc.init(sv->harena_bytes);
+    if (hipMalloc((void **)&sv->next_d, 8 * sizeof(int32_t)) != hipSuccess ||
+        hipMemset(sv->next_d, 0, 8 * sizeof(int32_t)) != hipSuccess)
         return bail(MF_EDEVICE, "device counter allocation failed");
     sv->idle_ticks = ctx->wall_hz / 1000ull * (uint64_t)sv->cfg.idle_ms;
     for (int q = 0; q < 4; q++) sv->slot_owner[q].assign(SERVE_CAP, nullptr);
@@ -212,12 +260,9 @@ extern "C" void mf_server_destroy(mf_server *sv)
             (void)hipStreamSynchronize(sv->kstream[q]);
             (void)hipStreamDestroy(sv->kstream[q]);
         }
-    if (sv->copy) {
-        (void)hipStreamSynchronize(sv->copy);
-        (void)hipStreamDestroy(sv->copy);
-    }
     for (int q = 0; q < 4; q++)
         if (sv->hq[q]) (void)hipHostFree(sv->hq[q]);
+    if (sv->harena) (void)hipHostFree(sv->harena);
     if (sv->next_d) (void)hipFree(sv->next_d);
     if (sv->region) dfree(sv->ctx, sv->region, sv->cfg.hbm_budget_bytes);
     for (auto &kv : sv->reqs) delete kv.second;
@@ -245,28 +290,60 @@ extern "C" mf_status mf_server_submit(mf_server *sv, const mf_graph *g, const mf
                           o.gr_freq_den > 0 && o.gr_freq_num >= 0 && o.gr_alpha >= 0 && o.gr_beta >= 0 &&
                           o.gr_round_charge >= 0 && o.max_rounds >= 0;
     if (shape_ok) {
+        r->G = batch_lanes(o.lanes_per_vertex, g->n, g->slots);
+        r->queue = 0;        // one queue; the serve kernel handles every lane count
+        r->bytes = request_bytes(g->n, g->slots, r->want_flow);
+        r->host_bytes = host_layout(g->n, g->slots).end;
+    }
+    const bool fits = shape_ok && r->bytes <= sv->cfg.hbm_budget_bytes && r->host_bytes <= sv->harena_bytes;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->ticket = sv->next_ticket++;
+        r->t_submit = Clock::now();
+        sv->reqs[r->ticket] = r;
+        sv->st.submitted++;
+        *ticket = r->ticket;
+        if (!fits) {
+            r->result.status = shape_ok ? MF_ENOMEM : MF_EINVAL;
+            r->state = COMPLETE;
+            r->t_done = Clock::now();
+            sv->st.rejected++;
+            sv->cv.notify_all();
+            return MF_OK;
+        }
+        // The graph goes straight into a staging slice when one is free and
+        // no earlier request is still waiting for one; otherwise into
+        // pageable memory, and the worker stages it at admission.  Pending
+        // requests stay in ticket order, so those holding a slice always
+        // precede those waiting for one.
+        r->state = STAGING;
+        if (sv->unstaged == 0 && sv->halloc.alloc(r->host_bytes, r->host_off))
+            r->staged = true;
+        else
+            sv->unstaged++;
+    }
+    // the copy runs on the caller's thread, without the lock
+    if (r->staged) {
+        stage_graph(sv, r, g->offsets, g->rev, g->head, g->cap);
+    } else {
         r->off.assign(g->offsets, g->offsets + g->n + 1);
         r->rev.assign(g->rev, g->rev + g->slots);
         r->head.assign(g->head, g->head + g->slots);
         r->cap.assign(g->cap, g->cap + g->slots);
-        r->G = batch_lanes(o.lanes_per_vertex, g->n, g->slots);
-        r->queue = r->G == 4 ? 0 : r->G == 8 ? 1 : r->G == 16 ? 2 : 3;
-        r->bytes = request_bytes(g->n, g->slots, r->want_flow);
     }
     std::lock_guard<std::mutex> lk(sv->mu);
-    r->ticket = sv->next_ticket++;
-    r->t_submit = Clock::now();
-    sv->reqs[r->ticket] = r;
-    sv->st.submitted++;
-    if (!shape_ok || r->bytes > sv->cfg.hbm_budget_bytes) {
-        r->result.status = shape_ok ? MF_ENOMEM : MF_EINVAL;
+    if (r->canceled) {                     // canceled while its graph was copied
+        drop_staging(sv, r);
+        r->result.status = MF_ECANCELED;
         r->state = COMPLETE;
         r->t_done = Clock::now();
-        sv->st.rejected++;
+        sv->st.canceled++;
     } else {
-        sv->pending.push_back(r);
+        r->state = PENDING;
+        auto pos = sv->pending.end();
+        while (pos != sv->pending.begin() && (*(pos - 1))->ticket > r->ticket) --pos;
+        sv->pending.insert(pos, r);
     }
-    *ticket = r->ticket;
     sv->cv.notify_all();
     return MF_OK;
 }
@@ -327,13 +404,14 @@ extern "C" mf_status mf_server_cancel(mf_server *sv, uint64_t ticket)
     if (it == sv->reqs.end()) return MF_ENOTFOUND;
     Request *r = it->second;
     if (r->state == COMPLETE) return MF_OK;
-    r->canceled = true;
+    r->canceled = true;    // STAGING, ADMITTING or PUBLISHED: completes as canceled when that step ends
     if (r->state == PENDING) {
         for (auto p = sv->pending.begin(); p != sv->pending.end(); ++p)
             if (*p == r) {
                 sv->pending.erase(p);
                 break;
             }
+        drop_staging(sv, r);
         r->result.status = MF_ECANCELED;
         r->state = COMPLETE;
         r->t_done = Clock::now();
@@ -350,49 +428,69 @@ extern "C" mf_status mf_server_get_stats(mf_server *sv, mf_server_stats *out)
     *out = sv->st;
     out->inflight = (int64_t)sv->inflight_list.size();
     out->queued = (int64_t)sv->pending.size();
-    out->bytes_in_use = sv->alloc.used();
+    out->bytes_in_use = sv->bytes_in_use;
     return MF_OK;
 }
 
 // ---------------------------------------------------------------------------
 // Worker
 
-// Copies the graph to its slice and publishes the request.  Called with the
-// lock held; the copies are synchronous on the copy stream.
+// The worker owns the device region, the allocator, the queues and the
+// in-flight list; the mutex guards what the API threads touch (the pending
+// queue, the ticket map, request states and results, the statistics).  Copies
+// and kernel launches happen without the mutex.
+
+// Copies a graph into the request's host staging slice.
+static void stage_graph(mf_server *sv, Request *r, const int64_t *off, const int64_t *rev, const int32_t *head,
+                        const int32_t *cap)
+{
+    uint8_t *hbase = sv->harena + r->host_off;
+    const HostLayout H = host_layout(r->n, r->S);
+    const size_t S = (size_t)r->S, N = (size_t)r->n;
+    memcpy(hbase, off, 8 * (N + 1));
+    if (S) {
+        memcpy(hbase + H.rev, rev, 8 * S);
+        memcpy(hbase + H.head, head, 4 * S);
+        memcpy(hbase + H.cap, cap, 4 * S);
+    }
+}
+
+// Writes the graph to its staging slice and publishes the request (without
+// the mutex; the request is in state ADMITTING).  Returns false if the
+// request does not fit now (it stays pending).
 static bool admit(mf_server *sv, Request *r)
 {
     size_t off;
     if ((int)sv->inflight_list.size() >= sv->cfg.max_inflight) return false;
     const int q = r->queue;
-    // the ring slot of this queue must be free
     const int32_t index = sv->published[q];
     if (sv->slot_owner[q][index % SERVE_CAP]) return false;
     if (!sv->alloc.alloc(r->bytes, off)) return false;
+    if (!r->staged) {
+        bool got;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            got = sv->halloc.alloc(r->host_bytes, r->host_off);
+        }
+        if (!got) {
+            sv->alloc.release(off, r->bytes);
+            return false;
+        }
+        stage_graph(sv, r, r->off.data(), r->rev.data(), r->head.data(), r->cap.data());
+        std::vector<int64_t>().swap(r->off);
+        std::vector<int64_t>().swap(r->rev);
+        std::vector<int32_t>().swap(r->head);
+        std::vector<int32_t>().swap(r->cap);
+        r->staged = true;
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->unstaged--;
+    }
     r->region_off = off;
     uint8_t *base = sv->region + off;
+    uint8_t *hbase = sv->harena + r->host_off;
     r->lay = layout_for(0, r->n, r->S, r->want_flow);
     const InstLayout &L = r->lay;
-    int64_t *off64 = (int64_t *)(base + L.end);
-    int64_t *rev64 = (int64_t *)(base + L.end + staging_rev(r->n));
-    const size_t S = (size_t)r->S, N = (size_t)r->n;
-    hipError_t e = hipMemcpyAsync(off64, r->off.data(), 8 * (N + 1), hipMemcpyHostToDevice, sv->copy);
-    if (e == hipSuccess && S) e = hipMemcpyAsync(rev64, r->rev.data(), 8 * S, hipMemcpyHostToDevice, sv->copy);
-    if (e == hipSuccess && S) e = hipMemcpyAsync(base + L.head, r->head.data(), 4 * S, hipMemcpyHostToDevice, sv->copy);
-    if (e == hipSuccess && S) e = hipMemcpyAsync(base + L.cap, r->cap.data(), 4 * S, hipMemcpyHostToDevice, sv->copy);
-    if (e == hipSuccess) e = hipStreamSynchronize(sv->copy);
-    if (e != hipSuccess) {
-        sv->alloc.release(off, r->bytes);
-        r->result.status = MF_EDEVICE;
-        r->state = COMPLETE;
-        r->t_done = Clock::now();
-        sv->err = hipGetErrorString(e);
-        return true;
-    }
-    // the host copy of the graph is no longer needed
-    std::vector<int64_t>().swap(r->off);
-    std::vector<int64_t>().swap(r->rev);
-    std::vector<int32_t>().swap(r->head);
-    std::vector<int32_t>().swap(r->cap);
+    const HostLayout H = host_layout(r->n, r->S);
     BatchItem it;
     memset(&it, 0, sizeof it);
     it.g.n = r->n;
@@ -417,11 +515,14 @@ static bool admit(mf_server *sv, Request *r)
     it.st.e = (int64_t *)(base + L.e);
     it.st.act = base + L.act;
     it.st.touched = base + L.touched;
-    it.ctl = nullptr;
     it.flow = r->want_flow ? (int32_t *)(base + L.flow) : nullptr;
     it.side = base + L.side;
-    it.off64 = off64;
-    it.rev64 = rev64;
+    it.off64 = (const int64_t *)hbase;
+    it.rev64 = (const int64_t *)(hbase + H.rev);
+    it.head_h = (const int32_t *)(hbase + H.head);
+    it.cap_h = (const int32_t *)(hbase + H.cap);
+    it.side_h = hbase;
+    it.flow_h = r->want_flow ? (int32_t *)(hbase + H.rev) : nullptr;
     it.G = r->G;
     it.preflow_only = (r->opt.flags & MF_PREFLOW_ONLY) ? 1 : 0;
     const mf_options &o = r->opt;
@@ -434,29 +535,31 @@ static bool admit(mf_server *sv, Request *r)
     it.p.dense_threshold = o.dense_threshold > 0 ? o.dense_threshold : std::max<int64_t>(512, r->n / 16);
     it.p.bu_factor = 8;
     it.p.hubdeg = 64 * r->G;
-    it.ctl = (Ctl *)(base + L.end + staging_ctl(r->n, r->S));
+    it.ctl = (Ctl *)(base + L.end);
     r->index = index;
     sv->slot_owner[q][index % SERVE_CAP] = r;
     ServeHostQueue *hq = sv->hq[q];
     hq->done[index % SERVE_CAP] = 0;
     hq->items[index % SERVE_CAP] = it;
     sv->published[q] = index + 1;
+    // the staging copies may use non-temporal stores: a full fence orders
+    // them before the publishing store
+    std::atomic_thread_fence(std::memory_order_seq_cst);
     __atomic_store_n(&hq->count, index + 1, __ATOMIC_RELEASE);
-    r->state = PUBLISHED;
     sv->inflight_list.push_back(r);
-    sv->st.admitted++;
-    sv->st.peak_bytes = std::max<size_t>(sv->st.peak_bytes, sv->alloc.used());
     return true;
 }
 
-static void finish(mf_server *sv, Request *r)
+// Reads the result of a finished request and its outputs from the staging
+// slice (without the mutex); frees its slices.
+static void finish(mf_server *sv, Request *r, bool canceled)
 {
     const int q = r->queue;
     ServeHostQueue *hq = sv->hq[q];
     const int slot = r->index % SERVE_CAP;
     const BatchResult br = hq->results[slot];
-    uint8_t *base = sv->region + r->region_off;
-    const InstLayout &L = r->lay;
+    const uint8_t *hbase = sv->harena + r->host_off;
+    const HostLayout H = host_layout(r->n, r->S);
     mf_result &R = r->result;
     R.lanes_per_vertex = r->G;
     R.status = br.status == 0 ? MF_OK : br.status == 1 ? MF_ETIMEOUT : br.status == 3 ? MF_EINVAL : MF_EDEVICE;
@@ -469,34 +572,24 @@ static void finish(mf_server *sv, Request *r)
     R.bfs_levels = br.levels;
     R.pushes = br.pushes;
     R.relabels = br.relabels;
-    R.ms_start = 0;
+    R.ms_start = br.t_solve > br.t_start ? 1e3 * (double)(br.t_solve - br.t_start) / (double)sv->ctx->wall_hz : 0;
     R.ms_end = 1e3 * (double)(br.t_end - br.t_start) / (double)sv->ctx->wall_hz;
-    if (!r->canceled && R.status == MF_OK) {
-        r->side.resize((size_t)r->n);
-        hipError_t e = hipMemcpyAsync(r->side.data(), base + L.side, (size_t)r->n, hipMemcpyDeviceToHost, sv->copy);
-        if (e == hipSuccess && r->want_flow && r->S) {
-            r->flow.resize((size_t)r->S);
-            e = hipMemcpyAsync(r->flow.data(), base + L.flow, 4 * (size_t)r->S, hipMemcpyDeviceToHost, sv->copy);
+    if (!canceled && R.status == MF_OK) {
+        r->side.assign(hbase, hbase + r->n);
+        if (r->want_flow && r->S) {
+            const int32_t *f = (const int32_t *)(hbase + H.rev);
+            r->flow.assign(f, f + r->S);
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(sv->copy);
-        if (e != hipSuccess) R.status = MF_EDEVICE;
-    }
-    if (r->canceled) {
-        R.status = MF_ECANCELED;
-        sv->st.canceled++;
-    } else {
-        sv->st.completed++;
     }
     sv->alloc.release(r->region_off, r->bytes);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->halloc.release(r->host_off, r->host_bytes);
     sv->slot_owner[q][slot] = nullptr;
-    r->state = COMPLETE;
-    r->t_done = Clock::now();
 }
 
 static void server_loop(mf_server *sv)
 {
     (void)hipSetDevice(sv->ctx->device);
-    std::unique_lock<std::mutex> lk(sv->mu);
     while (!sv->stop) {
         bool progress = false;
         // completions
@@ -504,43 +597,81 @@ static void server_loop(mf_server *sv)
             Request *r = sv->inflight_list[i];
             ServeHostQueue *hq = sv->hq[r->queue];
             const int d = __atomic_load_n(&hq->done[r->index % SERVE_CAP], __ATOMIC_ACQUIRE);
-            if (d == r->index + 1) {
-                finish(sv, r);
-                sv->inflight_list[i] = sv->inflight_list.back();
-                sv->inflight_list.pop_back();
-                progress = true;
-            } else {
+            if (d != r->index + 1) {
                 i++;
+                continue;
             }
-        }
-        if (progress) sv->cv.notify_all();
-        // admission in arrival order
-        while (!sv->pending.empty()) {
-            Request *r = sv->pending.front();
-            if (!admit(sv, r)) break;
-            sv->pending.pop_front();
-            progress = true;
-            if (r->state == COMPLETE) sv->cv.notify_all();
-        }
-        // keep a serve kernel running for every queue with published work
-        for (int q = 0; q < 4; q++) {
-            bool has_work = false;
-            for (Request *r : sv->inflight_list)
-                if (r->queue == q) {
-                    has_work = true;
-                    break;
+            bool canceled;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                canceled = r->canceled;
+            }
+            finish(sv, r, canceled);
+            sv->inflight_list[i] = sv->inflight_list.back();
+            sv->inflight_list.pop_back();
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                if (r->canceled) {
+                    r->result.status = MF_ECANCELED;
+                    sv->st.canceled++;
+                } else {
+                    sv->st.completed++;
                 }
-            if (!has_work) continue;
-            if (hipStreamQuery(sv->kstream[q]) == hipSuccess) {
-                int backlog = 0;
-                for (Request *r : sv->inflight_list) backlog += r->queue == q;
-                // enough workgroups for the work at hand plus room for arrivals
-                const int grid = std::max(1, std::min(sv->grid[q], std::max(16, 2 * backlog)));
-                if (launch_serve(4 << q, grid, sv->hq[q], sv->next_d + q, sv->idle_ticks, sv->kstream[q]) ==
-                    hipSuccess)
-                    sv->st.kernel_launches++;
+                r->state = COMPLETE;
+                r->t_done = Clock::now();
+                sv->bytes_in_use = sv->alloc.used();
+            }
+            sv->cv.notify_all();
+            progress = true;
+        }
+        // admission in arrival order
+        while (true) {
+            Request *r = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                if (sv->pending.empty()) break;
+                r = sv->pending.front();
+                sv->pending.pop_front();
+                r->state = ADMITTING;
+            }
+            const bool done = admit(sv, r);
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (!done && r->canceled) {            // canceled while being admitted
+                drop_staging(sv, r);
+                r->result.status = MF_ECANCELED;
+                r->state = COMPLETE;
+                r->t_done = Clock::now();
+                sv->st.canceled++;
+                sv->cv.notify_all();
+                progress = true;
+                continue;
+            }
+            if (!done) {
+                r->state = PENDING;
+                sv->pending.push_front(r);
+                break;
+            }
+            r->state = PUBLISHED;
+            sv->st.admitted++;
+            sv->bytes_in_use = sv->alloc.used();
+            sv->st.peak_bytes = std::max<size_t>(sv->st.peak_bytes, sv->bytes_in_use);
+            progress = true;
+        }
+        // keep the serve kernel running while requests are published
+        if (!sv->inflight_list.empty() && hipStreamQuery(sv->kstream[0]) == hipSuccess) {
+            const int grid = std::max(2, sv->grid[0]);
+            if (launch_serve(0, grid, sv->hq[0], sv->next_d, sv->idle_ticks, (int)sv->st.kernel_launches + 1,
+                             sv->kstream[0]) == hipSuccess) {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->st.kernel_launches++;
             }
         }
-        if (!progress) sv->cv.wait_for(lk, std::chrono::microseconds(100));
+        if (!progress) {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (sv->pending.empty() && sv->inflight_list.empty())
+                sv->cv.wait_for(lk, std::chrono::milliseconds(2));
+            else
+                sv->cv.wait_for(lk, std::chrono::microseconds(50));
+        }
     }
 }

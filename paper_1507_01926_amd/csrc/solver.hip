@@ -1,6 +1,6 @@
-// Host driver and C ABI of the maximum-flow library.
+// Host side and C ABI of the maximum-flow library.
 //
-// The driver runs the synchronous push-relabel loop of Sec. 3.1 (Listing 1):
+// The host loop runs the synchronous push-relabel loop of Sec. 3.1 (Listing 1):
 //   - init and source saturation;
 //   - global relabel first (W = infinity) and whenever the relabel work since
 //     the last one crosses the threshold of Sec. 3 (freq * W > alpha*n + m);
@@ -700,7 +700,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
         stats->ms_preflow = ms1;
         stats->ms_total = ms2;
         if (S.profile) {
-            // Algorithmic bytes (the per-unit model of the design notes):
+            // Algorithmic bytes per unit of work:
             //  discharge: 40 B per discharged vertex (list entry or flag, two
             //    offsets, label, excess, new label and excess, touched mark),
             //    13 B per slot of a discharged vertex (residual, head, head's
@@ -937,6 +937,10 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
     std::vector<int32_t> order;
     int boff[4], bcnt[4];
     for (int b = 0; b < 4; b++) {
+        // largest instances first: the longest solves start earliest
+        std::stable_sort(bucket[b].begin(), bucket[b].end(), [&](int32_t x, int32_t y) {
+            return graphs[x].n + graphs[x].slots > graphs[y].n + graphs[y].slots;
+        });
         boff[b] = (int)order.size();
         bcnt[b] = (int)bucket[b].size();
         order.insert(order.end(), bucket[b].begin(), bucket[b].end());

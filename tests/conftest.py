@@ -14,5 +14,6 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) on a machine without a GPU only when
-    # they were deselected implicitly; `-m gpu` on a GPU machine runs them all.
+    # they were deselected implicitly; `-m gpu` on a machine with a GPU runs
+    # them all.
     pass
