@@ -119,7 +119,34 @@ typedef struct {
      * (with MF_PROFILE the per-step times above stay 0 in this mode) */
     double ms_phase_kernel;
     int64_t phase_launches;
+    /* with MF_PROFILE, per kernel (index: mf_kernel_id): summed durations of
+     * its launches (HIP events recorded around each launch on the context's
+     * stream), number of launches and algorithmic bytes of those launches */
+    double kernel_ms[8];
+    int64_t kernel_launches[8];
+    int64_t kernel_bytes[8];
 } mf_stats;
+
+/* Kernels of the host-driven path that mf_stats profiles one by one.
+ * Algorithmic bytes per unit of work:
+ *   discharge (list / dense): 40 per discharged vertex, 13 per slot of a
+ *     discharged vertex, 16 per push, plus n per dense round (flags);
+ *   merge (list / dense): 41 per merged vertex, 4 per slot of a merged
+ *     vertex, 12 per push received, plus n per dense round;
+ *   top-down level: 12 per frontier vertex, 12 per slot examined, 8 per
+ *     vertex labelled;  hub expansion: 12 per hub, 12 per slot examined;
+ *   bottom-up level: 4 per vertex, 8 per unlabelled vertex, 12 per slot
+ *     examined, 8 per vertex labelled. */
+typedef enum {
+    MF_K_DISCHARGE_LIST = 0,
+    MF_K_DISCHARGE_DENSE = 1,
+    MF_K_MERGE_LIST = 2,
+    MF_K_MERGE_DENSE = 3,
+    MF_K_GR_TOPDOWN = 4,
+    MF_K_GR_HUB = 5,
+    MF_K_GR_BOTTOMUP = 6,
+    MF_K_COUNT = 7
+} mf_kernel_id;
 
 typedef struct mf_context mf_context;
 typedef struct mf_dgraph mf_dgraph;

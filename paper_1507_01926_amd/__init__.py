@@ -55,7 +55,13 @@ class mf_stats(ctypes.Structure):
         ("ms_global_relabel", ctypes.c_double)] + [(k, ctypes.c_int64) for k in (
         "discharge_launches", "merge_launches", "global_relabel_launches", "discharge_bytes",
         "merge_bytes", "global_relabel_bytes")] + [
-        ("ms_phase_kernel", ctypes.c_double), ("phase_launches", ctypes.c_int64)]
+        ("ms_phase_kernel", ctypes.c_double), ("phase_launches", ctypes.c_int64),
+        ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_int64 * 8),
+        ("kernel_bytes", ctypes.c_int64 * 8)]
+
+# kernel names of mf_stats.kernel_* in index order (mf_kernel_id)
+KERNEL_NAMES = ("k_discharge_list", "k_discharge_dense", "k_merge_list", "k_merge_dense", "k_gr_td",
+                "k_gr_hub", "k_gr_bu")
 
 
 class mf_result(ctypes.Structure):
@@ -149,7 +155,11 @@ def options(**kw) -> mf_options:
 
 
 def _stats_dict(s: mf_stats) -> dict:
-    return {k: getattr(s, k) for k, _ in mf_stats._fields_}
+    d = {}
+    for k, _ in mf_stats._fields_:
+        v = getattr(s, k)
+        d[k] = list(v) if k.startswith("kernel_") else v
+    return d
 
 
 class _HostGraph:

@@ -83,6 +83,22 @@ __global__ void k_validate(GraphView g, Ctl *ctl)
     if (err) atomicOr(&ctl->err, err);
 }
 
+// Degree figures that decide which global-relabel levels can meet a hub
+// vertex: the largest out-degree over the vertices other than s and t, and
+// the out-degrees of s and t (the BFS roots of the two phases).
+__global__ void k_degree_stats(GraphView g, Ctl *ctl)
+{
+    int mx = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const int deg = g.off[v + 1] - g.off[v];
+        if (v == g.s) ctl->deg_s = deg;
+        else if (v == g.t) ctl->deg_t = deg;
+        else mx = max(mx, deg);
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if (lane_id() == 0 && mx > 0) atomicMax(&ctl->maxdeg_inner, mx);
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation (Listing 1: d = 0, e = 0, f = 0, d(s) = n) and source
 // saturation (every arc out of s carries its capacity).
@@ -160,9 +176,15 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
         st.ctl->nh[2] = 0;
         st.ctl->na = 0;
         st.ctl->na2 = 0;
+        st.ctl->bfs_empty_level = 0x7fffffff;
+        st.ctl->gr_found = 0;
     }
 }
 
+// Top-down level.  Levels may be launched several at a time without the host
+// reading the frontier sizes in between: a level whose frontier is empty
+// records itself in bfs_empty_level and returns (every later level is empty
+// too, since it finds nothing to expand).
 template <int G>
 __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int level, int sink,
                                                int other, const int32_t *__restrict__ qin,
@@ -172,11 +194,14 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.ctl->nq[(level + 2) % 3] = 0;
         st.ctl->nh[(level + 1) % 3] = 0;
+        if (nq == 0) atomicMin(&st.ctl->bfs_empty_level, level);
     }
+    if (nq == 0) return;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
     const int next = level + 1;
     int64_t gslots = 0;
+    int claims = 0;
     MF_STAGE(stage);
     stage_init(stage);
     for (int i = blockIdx.x * groups + threadIdx.x / G; i < nq; i += gridDim.x * groups) {
@@ -196,6 +221,7 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
                 if (w != sink && w != other && st.d[w] == g.n && st.res[g.rev[a]] > 0) {
                     if (atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
+                        claims++;
                         st.dn[w] = next;
                     }
                 }
@@ -205,6 +231,7 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
     }
     stage_flush(stage, qout, &st.ctl->nq[next % 3]);
     block_add64(gslots, &st.ctl->gslots);
+    block_add64(claims, &st.ctl->gr_found);
 }
 
 // The hub vertices of a top-down level, each expanded by every block.
@@ -214,6 +241,7 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
     const int nh = st.ctl->nh[level % 3];
     const int next = level + 1;
     int64_t gslots = 0;
+    int claims = 0;
     MF_STAGE(stage);
     stage_init(stage);
     for (int h = 0; h < nh; h++) {
@@ -229,6 +257,7 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
                 if (w != sink && w != other && st.d[w] == g.n && st.res[g.rev[a]] > 0) {
                     if (atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
+                        claims++;
                         st.dn[w] = next;
                     }
                 }
@@ -237,7 +266,8 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
         }
     }
     stage_flush(stage, qout, &st.ctl->nq[next % 3]);
-    block_add64(gslots, &st.ctl->gslots);
+    block_add64(gslots, &st.ctl->hslots);
+    block_add64(claims, &st.ctl->gr_found);
 }
 
 __global__ __launch_bounds__(256) void k_gr_bu(GraphView g, StateView st, int level, int sink, int other)
@@ -505,6 +535,10 @@ void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int
 void launch_validate(GraphView g, Ctl *ctl, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, s, g, ctl);
+}
+void launch_degree_stats(GraphView g, Ctl *ctl, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_degree_stats, dim3(grid), dim3(256), 0, s, g, ctl);
 }
 void launch_init_state(GraphView g, StateView st, int grid, hipStream_t s)
 {

@@ -34,6 +34,11 @@ struct Ctl {
     int32_t p_status, p_lists;
     int64_t cut;           // cut capacity accumulator
     int64_t value;         // scratch for the host
+    int64_t hslots;        // slots examined by hub expansions (host-driven levels)
+    int32_t maxdeg_inner;  // largest out-degree over vertices other than s and t
+    int32_t deg_s, deg_t;  // out-degrees of s and t
+    int32_t bfs_empty_level;   // first top-down level of this relabel that found its frontier empty
+    int64_t gr_found;      // vertices labelled by top-down levels and hub expansions of this relabel
 };
 
 // Per-solve state.  Every array lives in device memory.

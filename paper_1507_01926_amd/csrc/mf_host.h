@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/maxflow.h"
 #include "mf_device.h"
@@ -21,6 +22,7 @@ struct mf_dgraph {
     int64_t slots = 0;
     int32_t *off = nullptr, *head = nullptr, *rev = nullptr, *cap = nullptr;
     size_t bytes = 0;
+    int32_t maxdeg_inner = 0, deg_s = 0, deg_t = 0;   // out-degrees (hub levels of the BFS)
     GraphView view() const
     {
         GraphView g;
@@ -55,9 +57,10 @@ struct mf_context {
     GridBar *bar = nullptr;    // device: persistent-kernel barrier
     uint64_t wall_hz = 100000000ull;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t pev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // profiling
+    hipEvent_t pev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // profiling
     hipStream_t bstream[4] = {nullptr, nullptr, nullptr, nullptr};                 // batch groups
     hipEvent_t bev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> lev;     // profiling of batched levels, created on first use
     Workspace ws;
     int num_cus = 256;
     std::string err;

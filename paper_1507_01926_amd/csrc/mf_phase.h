@@ -7,11 +7,14 @@
 
 namespace mf {
 
+// Grid barrier state: arrivals and the generation that waiting blocks poll
+// sit on separate 128-byte lines.
 struct GridBar {
     unsigned count;
+    int pad0[31];
     unsigned gen;
     int abort;
-    int pad;
+    int pad1[30];
 };
 
 struct PhaseParams {

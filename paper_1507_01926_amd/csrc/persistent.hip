@@ -36,14 +36,21 @@ __device__ __forceinline__ bool grid_sync(GridBar *bar, uint64_t limit_ticks)
             __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bar->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
+            // Waiting blocks back off (up to about 2000 cycles between
+            // polls): hundreds of blocks polling one line at full rate keep
+            // its L2 channel busy and slow the blocks still working.
             const uint64_t t0 = wall_clock64();
+            unsigned nap = 1, polls = 0;
             while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                if (wall_clock64() - t0 > limit_ticks) {
-                    __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
+                if ((++polls & 15) == 0) {
+                    if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                    if (wall_clock64() - t0 > limit_ticks) {
+                        __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
                 }
-                __builtin_amdgcn_s_sleep(1);
+                for (unsigned k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(1);
+                if (nap < 32) nap <<= 1;
             }
         }
         s_ok = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;

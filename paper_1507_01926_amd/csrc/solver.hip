@@ -40,6 +40,7 @@ void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, in
 void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s);
 void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s);
 void launch_compact_act(GraphView g, StateView st, int grid, hipStream_t s);
+void launch_degree_stats(GraphView g, Ctl *ctl, int grid, hipStream_t s);
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s);
 void launch_validate(GraphView g, Ctl *ctl, int grid, hipStream_t s);
@@ -169,6 +170,7 @@ void mf_context_destroy(mf_context *ctx)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : ctx->bev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto ev : ctx->lev) (void)hipEventDestroy(ev);
     for (auto bs : ctx->bstream)
         if (bs) (void)hipStreamDestroy(bs);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -273,11 +275,15 @@ extern "C" mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_
     }
     if (ctx->ctl_host->err == 0) {
         launch_validate(dg->view(), ctx->ctl, grid_for(S, 256, maxg), ctx->stream);
+        launch_degree_stats(dg->view(), ctx->ctl, grid_for(N, 256, maxg), ctx->stream);
         if ((st = read_ctl(ctx)) != MF_OK) {
             cleanup();
             mf_graph_free(ctx, dg);
             return st;
         }
+        dg->maxdeg_inner = ctx->ctl_host->maxdeg_inner;
+        dg->deg_s = ctx->ctl_host->deg_s;
+        dg->deg_t = ctx->ctl_host->deg_t;
     }
     cleanup();
     if (ctx->ctl_host->err) {
@@ -380,7 +386,17 @@ struct Solve {
     double ms_dis = 0, ms_mer = 0, ms_gr = 0, ms_phase = 0;
     int64_t n_dis = 0, n_mer = 0, n_gr = 0, n_phase = 0;
     int64_t dense_rounds = 0, bu_levels = 0, td_levels = 0, grs = 0;
+    double kms[MF_K_COUNT] = {};         // per kernel: event time, launches, algorithmic bytes
+    int64_t kn[MF_K_COUNT] = {}, kb[MF_K_COUNT] = {};
+    Ctl last;                            // counters at the previous readback
 };
+
+static void kernel_record(Solve &S, int k, double ms, int64_t bytes)
+{
+    S.kms[k] += ms;
+    S.kn[k]++;
+    S.kb[k] += bytes;
+}
 
 static float elapsed(hipEvent_t a, hipEvent_t b)
 {
@@ -401,6 +417,17 @@ static void prepare_working_set(Solve &S, int count, bool have_list, bool &dense
     }
 }
 
+// Events for per-kernel times inside a batch of speculative levels.
+static mf_status batch_events(mf_context *ctx, size_t count)
+{
+    while (ctx->lev.size() < count) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return fail(ctx, MF_EDEVICE, "hipEventCreate failed");
+        ctx->lev.push_back(e);
+    }
+    return MF_OK;
+}
+
 static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, int &na, bool &dense)
 {
     mf_context *ctx = S.ctx;
@@ -408,11 +435,82 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
     launch_gr_init(S.g, S.st, sink, grid_for(n, 256, S.maxgrid), ctx->stream);
     int64_t nq = 1;
     int64_t unvisited = n - 2;
+    int64_t found_before = 0;          // gr_found at the last readback
     int level = 0;
+    // Top-down levels launched per readback: 1 while the frontier grows
+    // fast (the grid and the choice of a bottom-up level follow its size),
+    // doubling up to 32 while it stays within a factor 2 of the last one.
+    int batch = 1;
     bool have_list = true;
     int32_t *qin = S.st.Q, *qout = S.st.Q2;
+    const int groups = 256 / S.G;
+    // A frontier holds the sink alone at level 0 and only vertices other
+    // than s and t later, so the hub expansion runs only where one of them
+    // can exceed the hub degree.
+    const int deg_sink = sink == S.dg->s ? S.dg->deg_s : S.dg->deg_t;
+    const bool hub_first = deg_sink > S.hubdeg;
+    const bool hub_later = S.dg->maxdeg_inner > S.hubdeg;
     while (nq > 0) {
         const bool bottom_up = nq * S.bu_factor > unvisited;
+        if (!bottom_up && have_list) {
+            // A batch of top-down levels with one readback at its end; the
+            // levels after the one that empties the frontier return at once.
+            const int K = batch;
+            const int grid = grid_for(K == 1 ? nq : std::max<int64_t>(4 * nq, 2048), groups, S.maxgrid);
+            int nl = 0;                // launches, with their kinds for the profile
+            int kinds[2 * 32];
+            if (S.profile) {
+                mf_status est = batch_events(ctx, 2 * 32 + 1);
+                if (est != MF_OK) return est;
+                HIPCHK(ctx, hipEventRecord(ctx->lev[0], ctx->stream));
+            }
+            for (int j = 0; j < K; j++) {
+                const int L = level + j;
+                launch_gr_td(S.G, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, grid, ctx->stream);
+                kinds[nl++] = MF_K_GR_TOPDOWN;
+                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[nl], ctx->stream));
+                if (L == 0 ? hub_first : hub_later) {
+                    launch_gr_hub(S.g, S.st, L, sink, other, qout, ctx->num_cus * 2, ctx->stream);
+                    kinds[nl++] = MF_K_GR_HUB;
+                    if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[nl], ctx->stream));
+                }
+                std::swap(qin, qout);
+            }
+            mf_status st = read_ctl(ctx);
+            if (st != MF_OK) return st;
+            const Ctl &c = *ctx->ctl_host;
+            const bool ended = c.bfs_empty_level < level + K;
+            const int ran = ended ? c.bfs_empty_level - level : K;   // levels with a non-empty frontier
+            const int64_t found = c.gr_found - found_before;
+            const int64_t nq_next = ended ? 0 : c.nq[(level + K) % 3];
+            if (S.profile) {
+                // bytes by the model of each kernel; the frontier sizes of the
+                // batch add up to nq + found - nq_next
+                const int64_t frontier = nq + found - nq_next;
+                int64_t td_bytes = 12 * frontier + 12 * (c.gslots - S.last.gslots) + 8 * found;
+                int64_t hub_bytes = 12 * (c.hslots - S.last.hslots);
+                for (int i = 0; i < nl; i++) {
+                    const int k = kinds[i];
+                    int64_t b = 0;
+                    if (k == MF_K_GR_TOPDOWN) { b = td_bytes; td_bytes = 0; }
+                    else { b = hub_bytes; hub_bytes = 0; }
+                    const double ms = elapsed(ctx->lev[i], ctx->lev[i + 1]);
+                    kernel_record(S, k, ms, b);
+                    S.ms_gr += ms;
+                }
+                S.n_gr += ran;
+                S.last = c;
+            }
+            S.td_levels += ran;
+            unvisited -= found;
+            found_before = c.gr_found;
+            level += ran;
+            batch = nq_next > 2 * nq ? 1 : std::min(32, 2 * batch);
+            nq = nq_next;
+            continue;
+        }
+        // one level at a time: bottom-up, or top-down after a bottom-up level
+        const bool hubs = level == 0 ? hub_first : hub_later;
         if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
         if (bottom_up) {
             S.bu_levels++;
@@ -420,25 +518,41 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             have_list = false;
         } else {
             S.td_levels++;
-            if (!have_list) {
-                HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
-                launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
-            }
-            const int groups = 256 / S.G;
+            HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
+            launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
+            if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
             launch_gr_td(S.G, S.g, S.st, level, sink, other, qin, qout, S.hubdeg,
                          grid_for(nq, groups, S.maxgrid), ctx->stream);
-            launch_gr_hub(S.g, S.st, level, sink, other, qout, ctx->num_cus * 2, ctx->stream);
+            if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[6], ctx->stream));
+            if (hubs) launch_gr_hub(S.g, S.st, level, sink, other, qout, ctx->num_cus * 2, ctx->stream);
             std::swap(qin, qout);
             have_list = true;
         }
         if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[5], ctx->stream));
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
+        const Ctl &c = *ctx->ctl_host;
+        const int64_t found = c.nq[(level + 1) % 3];
         if (S.profile) {
-            S.ms_gr += elapsed(ctx->pev[4], ctx->pev[5]);
+            const double ms = elapsed(ctx->pev[4], ctx->pev[5]);
+            S.ms_gr += ms;
             S.n_gr++;
+            const int64_t gs = c.gslots - S.last.gslots;
+            if (bottom_up) {
+                kernel_record(S, MF_K_GR_BOTTOMUP, ms, 4 * (int64_t)n + 8 * unvisited + 12 * gs + 8 * found);
+            } else {
+                const double ms_td = elapsed(ctx->pev[4], ctx->pev[6]);
+                kernel_record(S, MF_K_GR_TOPDOWN, ms_td, 12 * nq + 12 * gs + 8 * found);
+                if (hubs) {
+                    const int64_t nh = c.nh[level % 3];
+                    kernel_record(S, MF_K_GR_HUB, elapsed(ctx->pev[6], ctx->pev[5]),
+                                  12 * nh + 12 * (c.hslots - S.last.hslots));
+                }
+            }
+            S.last = c;
         }
-        nq = ctx->ctl_host->nq[(level + 1) % 3];
+        found_before = c.gr_found;
+        nq = found;
         unvisited -= nq;
         level++;
     }
@@ -496,10 +610,19 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
         if (S.profile) {
-            S.ms_dis += elapsed(ctx->pev[0], ctx->pev[1]);
-            S.ms_mer += elapsed(ctx->pev[2], ctx->pev[3]);
+            const double md = elapsed(ctx->pev[0], ctx->pev[1]), mm = elapsed(ctx->pev[2], ctx->pev[3]);
+            S.ms_dis += md;
+            S.ms_mer += mm;
             S.n_dis++;
             S.n_mer++;
+            const Ctl &c = *ctx->ctl_host;
+            const int64_t p = c.pushes - S.last.pushes;
+            const int64_t flags = dense ? n : 0;
+            kernel_record(S, dense ? MF_K_DISCHARGE_DENSE : MF_K_DISCHARGE_LIST, md,
+                          40 * (c.dverts - S.last.dverts) + 13 * (c.dslots - S.last.dslots) + 16 * p + flags);
+            kernel_record(S, dense ? MF_K_MERGE_DENSE : MF_K_MERGE_LIST, mm,
+                          41 * (c.mverts - S.last.mverts) + 4 * (c.mslots - S.last.mslots) + 12 * p + flags);
+            S.last = c;
         }
         if (dense) S.dense_rounds++;
         W += ctx->ctl_host->work + o.gr_round_charge;
@@ -611,6 +734,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     if ((st = ensure_workspace(ctx, dg->n, dg->slots)) != MF_OK) return st;
 
     Solve S;
+    memset(&S.last, 0, sizeof S.last);
     S.ctx = ctx;
     S.dg = dg;
     S.g = dg->view();
@@ -730,7 +854,12 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
             stats->global_relabel_launches = S.n_gr;
             stats->discharge_bytes = 40 * c.dverts + 13 * c.dslots + 16 * c.pushes + S.dense_rounds * (int64_t)n;
             stats->merge_bytes = 41 * c.mverts + 4 * c.mslots + 12 * c.pushes + S.dense_rounds * (int64_t)n;
-            stats->global_relabel_bytes = 12 * c.gslots + S.grs * 9 * (int64_t)n + S.bu_levels * 4 * (int64_t)n;
+            stats->global_relabel_bytes = 12 * (c.gslots + c.hslots) + S.grs * 9 * (int64_t)n + S.bu_levels * 4 * (int64_t)n;
+            for (int k = 0; k < MF_K_COUNT; k++) {
+                stats->kernel_ms[k] = S.kms[k];
+                stats->kernel_launches[k] = S.kn[k];
+                stats->kernel_bytes[k] = S.kb[k];
+            }
         }
     }
     return timed_out ? fail(ctx, MF_ETIMEOUT, "round limit %lld reached", (long long)o.max_rounds) : MF_OK;
