@@ -43,6 +43,40 @@ def tuned_schedule(g) -> dict:
     return dict(gr_round_charge=max(1, thr // 128))
 
 
+def kernel_source_sha() -> str:
+    """sha256 over the HIP sources of the library (counters taken on other
+    sources no longer describe the kernels)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1507_01926_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary kept under profiles/, if it was taken on the current
+    sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_model() -> str:
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
@@ -170,6 +204,9 @@ def main():
     ap.add_argument("--stream", type=int, default=256,
                     help="instances of the batched/served stream leg (0 = skip)")
     ap.add_argument("--stream-nmax", type=float, default=1e5)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the solves, copy a buffer of this size on the device (a dispatch of known "
+                         "traffic that scales the HBM counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X "
@@ -189,6 +226,12 @@ def main():
     flow = torch.empty(max(1, g.slots), dtype=torch.int32, device=dev)
     side = torch.empty(g.n, dtype=torch.uint8, device=dev)
     opt = mf.options(profile=True, persistent=args.persistent, **sched)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] warmup x{args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         dg.solve(opt, flow.data_ptr(), side.data_ptr())
@@ -236,7 +279,8 @@ def main():
                    "n": g.n, "arcs": g.m_arcs, "slots": g.slots,
                    "schedule": sched or "paper (freq 1/2, alpha 6, beta 12)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, args.workload),
                      "launches_per_step": launches_k / args.steps,
                      "alg_bytes_per_launch": bytes_k / max(1, launches_k),
                      "avg_launch_us": 1e3 * ms_k / max(1, launches_k)},

@@ -98,7 +98,9 @@ typedef struct {
     int32_t lanes_per_merge;     /* lanes that merge one vertex's excess: 0 = automatic */
     int32_t dense_threshold;     /* working sets above this size run in dense mode: 0 = automatic */
     int32_t blocks_per_cu;       /* persistent kernel blocks per compute unit: 0 = occupancy limit */
-    int32_t reserved[3];
+    int32_t lanes_per_bfs;       /* lanes that expand one frontier vertex in a top-down BFS level of
+                                    the global relabel: 0 = automatic, else 1..64, power of 2 */
+    int32_t reserved[2];
 } mf_options;
 
 typedef struct {
@@ -122,17 +124,19 @@ typedef struct {
     /* with MF_PROFILE, per kernel (index: mf_kernel_id): summed durations of
      * its launches (HIP events recorded around each launch on the context's
      * stream), number of launches and algorithmic bytes of those launches */
-    double kernel_ms[8];
-    int64_t kernel_launches[8];
-    int64_t kernel_bytes[8];
+    double kernel_ms[12];
+    int64_t kernel_launches[12];
+    int64_t kernel_bytes[12];
 } mf_stats;
 
 /* Kernels of the host-driven path that mf_stats profiles one by one.
  * Algorithmic bytes per unit of work:
  *   discharge (list / dense): 40 per discharged vertex, 13 per slot of a
- *     discharged vertex, 16 per push, plus n per dense round (flags);
+ *     discharged vertex, 16 per push;
  *   merge (list / dense): 41 per merged vertex, 4 per slot of a merged
- *     vertex, 12 per push received, plus n per dense round;
+ *     vertex, 12 per push received;
+ *   flag compaction (dense rounds list their working set and their touched
+ *     vertices): n per pass plus 4 per listed vertex;
  *   top-down level: 12 per frontier vertex, 12 per slot examined, 8 per
  *     vertex labelled;  hub expansion: 12 per hub, 12 per slot examined;
  *   bottom-up level: 4 per vertex, 8 per unlabelled vertex, 12 per slot
@@ -145,7 +149,8 @@ typedef enum {
     MF_K_GR_TOPDOWN = 4,
     MF_K_GR_HUB = 5,
     MF_K_GR_BOTTOMUP = 6,
-    MF_K_COUNT = 7
+    MF_K_COMPACT = 7,
+    MF_K_COUNT = 8
 } mf_kernel_id;
 
 typedef struct mf_context mf_context;

@@ -43,7 +43,8 @@ class mf_options(ctypes.Structure):
                 ("gr_round_charge", ctypes.c_int64), ("max_rounds", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("lanes_per_vertex", ctypes.c_int32),
                 ("lanes_per_merge", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("blocks_per_cu", ctypes.c_int32), ("lanes_per_bfs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class mf_stats(ctypes.Structure):
@@ -56,12 +57,12 @@ class mf_stats(ctypes.Structure):
         "discharge_launches", "merge_launches", "global_relabel_launches", "discharge_bytes",
         "merge_bytes", "global_relabel_bytes")] + [
         ("ms_phase_kernel", ctypes.c_double), ("phase_launches", ctypes.c_int64),
-        ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_int64 * 8),
-        ("kernel_bytes", ctypes.c_int64 * 8)]
+        ("kernel_ms", ctypes.c_double * 12), ("kernel_launches", ctypes.c_int64 * 12),
+        ("kernel_bytes", ctypes.c_int64 * 12)]
 
 # kernel names of mf_stats.kernel_* in index order (mf_kernel_id)
 KERNEL_NAMES = ("k_discharge_list", "k_discharge_dense", "k_merge_list", "k_merge_dense", "k_gr_td",
-                "k_gr_hub", "k_gr_bu")
+                "k_gr_hub", "k_gr_bu", "k_compact_flags")
 
 
 class mf_result(ctypes.Structure):

@@ -323,19 +323,6 @@ __global__ void k_gr_rebuild(GraphView g, StateView st, int sink, int other)
     block_add32(cnt, &st.ctl->na2);
 }
 
-// Working-set list from the activity flags.
-__global__ __launch_bounds__(256) void k_compact_act(GraphView g, StateView st)
-{
-    MF_STAGE(stage);
-    stage_init(stage);
-    for (int base = blockIdx.x * blockDim.x; base < g.n; base += gridDim.x * blockDim.x) {
-        const int v = base + threadIdx.x;
-        const bool p = v < g.n && st.act[v];
-        stage_append(stage, p, v, st.A, &st.ctl->na);
-    }
-    stage_flush(stage, st.A, &st.ctl->na);
-}
-
 // ---------------------------------------------------------------------------
 // Discharge (Listing 1, the loop over the working set).
 //
@@ -345,10 +332,12 @@ __global__ __launch_bounds__(256) void k_compact_act(GraphView g, StateView st)
 // the kernels walk all vertices: the working set is act[], and touched[]
 // marks the vertices to merge, which avoids list appends altogether.
 
-// List mode: the working set is A[0 .. na).
+// List mode: the working set is A[0 .. na).  In a batch of speculative rounds
+// a round after the one that stopped the batch does nothing.
 template <int G>
 __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView st, RoundParams p)
 {
+    if (st.ctl->batch_stop) return;
     const int na = st.ctl->na;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
@@ -358,27 +347,20 @@ __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView s
     discharge_flush(st, p, acc);
 }
 
-// Dense mode: every wave reads 64 activity flags, and its 64/G groups take the
-// active vertices among them in turn (compaction inside the wave, no lists).
+// Dense mode: the working set is act[], which k_compact_flags has listed in
+// A[0 .. na) (in any order); the groups take the listed vertices in turn, so
+// active vertices that cluster in one region of the graph still spread over
+// the whole grid.  Pushes mark their heads in touched[] instead of appending
+// candidates.
 template <int G>
 __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView st, RoundParams p)
 {
-    constexpr int GPW = 64 / G;
-    const int lane = lane_id();
-    const int gl = lane & (G - 1);
-    const int grp = lane / G;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int na = st.ctl->na;
+    const int gl = threadIdx.x & (G - 1);
+    const int groups = blockDim.x / G;
     DisAcc acc;
-    for (int base = wave * 64; base < g.n; base += nwaves * 64) {
-        const int v0 = base + lane;
-        const uint64_t mask = __ballot(v0 < g.n && st.act[v0] != 0);
-        const int cnt = __popcll(mask);
-        for (int k0 = 0; k0 < cnt; k0 += GPW) {
-            const int k = k0 + grp;
-            if (k < cnt) discharge_vertex<G, true>(g, st, p, base + nth_set_bit(mask, k), gl, acc);
-        }
-    }
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups)
+        discharge_vertex<G, true>(g, st, p, st.A[i], gl, acc);
     discharge_flush(st, p, acc);
 }
 
@@ -392,51 +374,144 @@ __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView 
 template <int G>
 __global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, int sink, int other)
 {
+    if (st.ctl->batch_stop) return;
     const int nc = st.ctl->nc;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
     MerAcc acc;
+    MF_STAGE(stage);
+    stage_init(stage);
     for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups) {
         const int w = st.C[i];
         if (st.owner[w] != i) continue;
-        merge_vertex<G, false>(g, st, w, gl, sink, other, acc);
+        merge_vertex<G, false>(g, st, w, gl, sink, other, acc, &stage);
     }
+    stage_flush(stage, st.A2, &st.ctl->na2);
     merge_flush(st, false, acc);
 }
 
+// Dense mode: the touched vertices, listed in C[0 .. nc) by k_compact_flags.
 template <int G>
 __global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, int sink, int other)
 {
-    constexpr int GPW = 64 / G;
-    const int lane = lane_id();
-    const int gl = lane & (G - 1);
-    const int grp = lane / G;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int nc = st.ctl->nc;
+    const int gl = threadIdx.x & (G - 1);
+    const int groups = blockDim.x / G;
     MerAcc acc;
-    for (int base = wave * 64; base < g.n; base += nwaves * 64) {
-        const int v0 = base + lane;
-        const uint64_t mask = __ballot(v0 < g.n && st.touched[v0] != 0);
-        const int cnt = __popcll(mask);
-        for (int k0 = 0; k0 < cnt; k0 += GPW) {
-            const int k = k0 + grp;
-            if (k < cnt) merge_vertex<G, true>(g, st, base + nth_set_bit(mask, k), gl, sink, other, acc);
-        }
-    }
+    MF_STAGE(stage);
+    stage_init(stage);
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups)
+        merge_vertex<G, true>(g, st, st.C[i], gl, sink, other, acc, &stage);
+    stage_flush(stage, st.A2, &st.ctl->na2);
     merge_flush(st, true, acc);
 }
 
-__global__ void k_round_reset(Ctl *ctl)
+// Lists the vertices whose flag is set (in any order) and adds their number
+// to *count.  Each lane tests 16 flags with one 16-byte load; a block scan
+// places the entries and one atomic per block reserves their range.
+// flags must be 16-byte aligned.
+__global__ __launch_bounds__(256) void k_compact_flags(const uint8_t *__restrict__ flags, int n,
+                                                      int32_t *__restrict__ list, int32_t *count)
+{
+    __shared__ int s_wave[4];
+    __shared__ int s_base;
+    const int nchunks = (n + 15) >> 4;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    for (int c0 = blockIdx.x * 256; c0 < nchunks; c0 += gridDim.x * 256) {
+        const int c = c0 + threadIdx.x;
+        unsigned bits = 0;
+        if (c < nchunks) {
+            if (16 * c + 16 <= n) {
+                const uint4 q = ((const uint4 *)flags)[c];
+                const unsigned wds[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+#pragma unroll
+                    for (int b = 0; b < 4; b++)
+                        if ((wds[k] >> (8 * b)) & 0xffu) bits |= 1u << (4 * k + b);
+            } else {
+                for (int j = 0; 16 * c + j < n; j++)
+                    if (flags[16 * c + j]) bits |= 1u << j;
+            }
+        }
+        const int cnt = __popc(bits);
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) s_wave[wv] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int k = 0; k < 4; k++) {
+                const int t = s_wave[k];
+                s_wave[k] = tot;
+                tot += t;
+            }
+            s_base = tot ? atomicAdd(count, tot) : 0;
+        }
+        __syncthreads();
+        int pos = s_base + s_wave[wv] + incl - cnt;
+        while (bits) {
+            const int j = __ffs(bits) - 1;
+            bits &= bits - 1;
+            list[pos++] = 16 * c + j;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_round_reset(Ctl *ctl, int dense)
 {
     ctl->nc = 0;
     ctl->na2 = 0;
     ctl->work = 0;
+    ctl->batch_stop = 0;
+    if (dense) ctl->na = 0;        // the dense round lists its working set again
 }
 
 __global__ void k_round_end(Ctl *ctl)
 {
     ctl->na = ctl->na2;
     ctl->na2 = 0;
+}
+
+// Speculative list rounds: the host launches several rounds of list mode
+// without reading the counters in between.  k_round_begin opens a round
+// (the first one of the batch clears the stop flag and the round count);
+// k_round_close adds the round's relabel work and charge to W and stops the
+// batch when the next round must not run as a list round: its working set
+// is empty or above the dense threshold, or W calls for a global relabel
+// (the conditions the host checks after a single round).  A round that does
+// not stop the batch makes the next working set current (na := na2).
+__global__ void k_round_begin(Ctl *ctl, int first)
+{
+    if (first) {
+        ctl->batch_stop = 0;
+        ctl->batch_rounds = 0;
+    } else if (ctl->batch_stop) {
+        return;
+    }
+    ctl->nc = 0;
+    ctl->na2 = 0;
+    ctl->work = 0;
+}
+
+__global__ void k_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num,
+                              int64_t freq_den, int64_t gr_threshold, int64_t dense_threshold)
+{
+    if (ctl->batch_stop) return;
+    const int64_t W = (first ? W0 : ctl->batch_W) + ctl->work + charge;
+    ctl->batch_W = W;
+    ctl->batch_rounds++;
+    const int64_t next = ctl->na2;
+    if (next == 0 || next > dense_threshold || freq_num * W > freq_den * gr_threshold) {
+        ctl->batch_stop = 1;
+        return;
+    }
+    ctl->na = ctl->na2;
 }
 
 // ---------------------------------------------------------------------------
@@ -523,9 +598,13 @@ void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int 
 {
     hipLaunchKernelGGL(k_gr_collect, dim3(grid), dim3(256), 0, s, g, st, level, qout);
 }
-void launch_compact_act(GraphView g, StateView st, int grid, hipStream_t s)
+void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact_act, dim3(grid), dim3(256), 0, s, g, st);
+    const int chunks = (n + 15) / 16;
+    int grid = (chunks + 255) / 256;
+    if (grid > maxgrid) grid = maxgrid;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_compact_flags, dim3(grid), dim3(256), 0, s, flags, n, list, count);
 }
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s)
@@ -556,13 +635,23 @@ void launch_gr_rebuild(GraphView g, StateView st, int sink, int other, int grid,
 {
     hipLaunchKernelGGL(k_gr_rebuild, dim3(grid), dim3(256), 0, s, g, st, sink, other);
 }
-void launch_round_reset(Ctl *ctl, hipStream_t s)
+void launch_round_reset(Ctl *ctl, bool dense, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, ctl);
+    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, ctl, dense ? 1 : 0);
 }
 void launch_round_end(Ctl *ctl, hipStream_t s)
 {
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, ctl);
+}
+void launch_round_begin(Ctl *ctl, int first, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, s, ctl, first);
+}
+void launch_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num, int64_t freq_den,
+                        int64_t gr_threshold, int64_t dense_threshold, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round_close, dim3(1), dim3(1), 0, s, ctl, first, W0, charge, freq_num, freq_den,
+                       gr_threshold, dense_threshold);
 }
 void launch_side(GraphView g, const int32_t *d, uint8_t *side, int grid, hipStream_t s)
 {

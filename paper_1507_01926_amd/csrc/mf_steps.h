@@ -169,13 +169,12 @@ __device__ __forceinline__ void discharge_flush(StateView &st, const RoundParams
 }
 
 struct MerAcc {
-    int cnt = 0;
     int64_t mverts = 0, mslots = 0;
 };
 
 template <int G, bool DENSE>
 __device__ __forceinline__ void merge_vertex(const GraphView &g, StateView &st, int w, int gl, int sink,
-                                             int other, MerAcc &acc)
+                                             int other, MerAcc &acc, Stage *sg)
 {
     const int beg = g.off[w], end = g.off[w + 1];
     if (gl == 0) {
@@ -200,17 +199,19 @@ __device__ __forceinline__ void merge_vertex(const GraphView &g, StateView &st, 
         st.d[w] = dnew;
         pa = w != sink && w != other && e > 0 && dnew < g.n;
         st.act[w] = pa;
-        if (DENSE) {
-            st.touched[w] = 0;
-            acc.cnt += pa;
-        }
+        if (DENSE) st.touched[w] = 0;
     }
-    if (!DENSE) wave_append(pa, w, st.A2, &st.ctl->na2);
+    // the next working set, listed in A2 (each vertex is merged once); with a
+    // stage the entries collect in LDS and the caller flushes them
+    if (sg)
+        stage_append(*sg, pa, w, st.A2, &st.ctl->na2);
+    else
+        wave_append(pa, w, st.A2, &st.ctl->na2);
 }
 
 __device__ __forceinline__ void merge_flush(StateView &st, bool dense, MerAcc &acc)
 {
-    if (dense) block_add32(acc.cnt, &st.ctl->na2);
+    (void)dense;
     block_add64(acc.mverts, &st.ctl->mverts);
     block_add64(acc.mslots, &st.ctl->mslots);
 }

@@ -309,6 +309,7 @@ __device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const 
             discharge_flush(sr, rp, dacc);
             if (!tm.sync()) goto aborted;
             MerAcc macc;
+            stage_init(stage);
             if (dense) {
                 for (int base = wave * 64; base < n; base += nwaves * 64) {
                     const int v0 = base + lane;
@@ -316,7 +317,8 @@ __device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const 
                     const int cnt = __popcll(mask);
                     for (int k0 = 0; k0 < cnt; k0 += GPW) {
                         const int k = k0 + grp;
-                        if (k < cnt) merge_vertex<G, true>(g, sr, base + nth_set_bit(mask, k), gl, sink, other, macc);
+                        if (k < cnt)
+                            merge_vertex<G, true>(g, sr, base + nth_set_bit(mask, k), gl, sink, other, macc, &stage);
                     }
                 }
             } else {
@@ -324,9 +326,10 @@ __device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const 
                 for (int i = brank * groups + threadIdx.x / G; i < nc; i += nblocks * groups) {
                     const int w = st.C[i];
                     if (st.owner[w] != i) continue;
-                    merge_vertex<G, false>(g, sr, w, gl, sink, other, macc);
+                    merge_vertex<G, false>(g, sr, w, gl, sink, other, macc, &stage);
                 }
             }
+            stage_flush(stage, sr.A2, &sr.ctl->na2);
             merge_flush(sr, dense, macc);
             if (!tm.sync()) goto aborted;
             const int nxt = ld32(&rc->na2);
@@ -558,7 +561,7 @@ __device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *ou
             const int cnt = __popcll(mask);
             for (int k0 = 0; k0 < cnt; k0 += GPW) {
                 const int k = k0 + grp;
-                if (k < cnt) merge_vertex<G, true>(g, st, base + nth_set_bit(mask, k), gl, g.t, g.s, macc);
+                if (k < cnt) merge_vertex<G, true>(g, st, base + nth_set_bit(mask, k), gl, g.t, g.s, macc, nullptr);
             }
         }
         merge_flush(st, true, macc);

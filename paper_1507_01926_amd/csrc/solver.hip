@@ -39,8 +39,11 @@ void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, in
                    hipStream_t s);
 void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s);
 void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s);
-void launch_compact_act(GraphView g, StateView st, int grid, hipStream_t s);
+void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s);
 void launch_degree_stats(GraphView g, Ctl *ctl, int grid, hipStream_t s);
+void launch_round_begin(Ctl *ctl, int first, hipStream_t s);
+void launch_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num, int64_t freq_den,
+                        int64_t gr_threshold, int64_t dense_threshold, hipStream_t s);
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s);
 void launch_validate(GraphView g, Ctl *ctl, int grid, hipStream_t s);
@@ -48,7 +51,7 @@ void launch_init_state(GraphView g, StateView st, int grid, hipStream_t s);
 void launch_saturate(GraphView g, StateView st, int grid, hipStream_t s);
 void launch_gr_init(GraphView g, StateView st, int sink, int grid, hipStream_t s);
 void launch_gr_rebuild(GraphView g, StateView st, int sink, int other, int grid, hipStream_t s);
-void launch_round_reset(Ctl *ctl, hipStream_t s);
+void launch_round_reset(Ctl *ctl, bool dense, hipStream_t s);
 void launch_round_end(Ctl *ctl, hipStream_t s);
 void launch_side(GraphView g, const int32_t *d, uint8_t *side, int grid, hipStream_t s);
 void launch_cut(GraphView g, const uint8_t *side, Ctl *ctl, int grid, hipStream_t s);
@@ -80,6 +83,7 @@ void mf_options_default(mf_options *o)
     o->flags = 0;
     o->lanes_per_vertex = 0;
     o->lanes_per_merge = 0;
+    o->lanes_per_bfs = 0;
 }
 
 const char *mf_version(void) { return "mi355x-maxflow 0.1 (gfx950)"; }
@@ -368,13 +372,37 @@ static int pick_lanes(int requested, int64_t n, int64_t slots)
     return std::max(G, 4);
 }
 
+// Automatic lane counts of the host-driven path, from sweeps on the grid,
+// layered and R-MAT families: graphs with hub vertices (a vertex other than
+// s and t of degree above 64 times the average) discharge and expand with 32
+// lanes; otherwise a discharge uses 4 lanes up to an average degree of 12
+// (more lanes per vertex mean fewer vertices per wave, and the passes over a
+// vertex's slots are short), and a top-down BFS level 8 lanes (4 below an
+// average degree of 4).
+static void auto_lanes(const mf_dgraph *dg, int &G, int &Gb)
+{
+    const double avg = dg->n > 0 ? (double)dg->slots / (double)dg->n : 1.0;
+    if ((double)dg->maxdeg_inner > 64.0 * std::max(1.0, avg)) {
+        G = 32;
+        Gb = 32;
+        return;
+    }
+    if (avg <= 12.0) {
+        G = 4;
+    } else {
+        G = 4;
+        while (G < avg / 2 && G < 32) G <<= 1;
+    }
+    Gb = avg <= 4.0 ? 4 : 8;
+}
+
 struct Solve {
     mf_context *ctx;
     const mf_dgraph *dg;
     GraphView g;
     StateView st;
     mf_options opt;
-    int G, Gm;
+    int G, Gm, Gb;             // lanes per vertex: discharge, merge, top-down BFS level
     int maxgrid;
     int64_t avg_deg_ceil;
     int64_t dense_threshold;   // working sets larger than this run in dense mode
@@ -413,7 +441,7 @@ static void prepare_working_set(Solve &S, int count, bool have_list, bool &dense
     dense = (int64_t)count > S.dense_threshold;
     if (!dense && !have_list) {
         (void)hipMemsetAsync(&S.ctx->ctl->na, 0, sizeof(int32_t), S.ctx->stream);
-        launch_compact_act(S.g, S.st, grid_for(S.g.n, 256, S.maxgrid), S.ctx->stream);
+        launch_compact_flags(S.st.act, S.g.n, S.st.A, &S.ctx->ctl->na, S.maxgrid, S.ctx->stream);
     }
 }
 
@@ -443,7 +471,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
     int batch = 1;
     bool have_list = true;
     int32_t *qin = S.st.Q, *qout = S.st.Q2;
-    const int groups = 256 / S.G;
+    const int groups = 256 / S.Gb;
     // A frontier holds the sink alone at level 0 and only vertices other
     // than s and t later, so the hub expansion runs only where one of them
     // can exceed the hub degree.
@@ -466,7 +494,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             }
             for (int j = 0; j < K; j++) {
                 const int L = level + j;
-                launch_gr_td(S.G, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, grid, ctx->stream);
+                launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, grid, ctx->stream);
                 kinds[nl++] = MF_K_GR_TOPDOWN;
                 if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[nl], ctx->stream));
                 if (L == 0 ? hub_first : hub_later) {
@@ -521,7 +549,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
             launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
             if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
-            launch_gr_td(S.G, S.g, S.st, level, sink, other, qin, qout, S.hubdeg,
+            launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg,
                          grid_for(nq, groups, S.maxgrid), ctx->stream);
             if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[6], ctx->stream));
             if (hubs) launch_gr_hub(S.g, S.st, level, sink, other, qout, ctx->num_cus * 2, ctx->stream);
@@ -578,11 +606,15 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
     int64_t W = 0;
     int na = 0;
     bool dense = false;
+    int rbatch = 1;              // list rounds per readback: doubles up to 16 while no round stops a batch
+    bool list_ready = false;     // the working set is listed in A (else only flagged in act)
     while (true) {
         bool just = false;
         if (force || o.gr_freq_num * W > o.gr_freq_den * (o.gr_alpha * n + m)) {
             mf_status st = global_relabel(S, sink, other, ps, na, dense);
             if (st != MF_OK) return st;
+            list_ready = !dense;     // a list-mode working set was compacted from the flags
+            rbatch = 1;
             W = 0;
             force = false;
             just = true;
@@ -593,46 +625,118 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             continue;
         }
         if (max_rounds > 0 && ps.rounds >= max_rounds) return MF_ETIMEOUT;
-        launch_round_reset(ctx->ctl, ctx->stream);
-        const int groups = 256 / S.G;
-        const int64_t dgrid_items = dense ? n : na;
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[0], ctx->stream));
-        launch_discharge(S.G, dense, S.g, S.st, o.gr_beta, sink, grid_for(dgrid_items, groups, S.maxgrid),
-                         ctx->stream);
-        if (S.profile) {
-            HIPCHK(ctx, hipEventRecord(ctx->pev[1], ctx->stream));
-            HIPCHK(ctx, hipEventRecord(ctx->pev[2], ctx->stream));
+        if (!dense) {
+            // Speculative list rounds: up to `rbatch` rounds with one readback;
+            // the round that must be followed by a global relabel, a dense
+            // round or an empty working set stops the rest.
+            int K = rbatch;
+            if (max_rounds > 0) K = (int)std::min<int64_t>(K, max_rounds - ps.rounds);
+            const int groups = 256 / S.G;
+            const int dgrid = grid_for(std::min<int64_t>(S.dense_threshold, 4 * (int64_t)na + 2048), groups,
+                                       S.maxgrid);
+            const int mgrid = grid_for(std::min<int64_t>(S.dense_threshold, 4 * (int64_t)na + 2048) *
+                                           (1 + S.avg_deg_ceil), 256 / S.Gm, S.maxgrid);
+            if (S.profile) {
+                mf_status est = batch_events(ctx, 3 * 16);
+                if (est != MF_OK) return est;
+            }
+            StateView sj = S.st;
+            for (int j = 0; j < K; j++) {
+                launch_round_begin(ctx->ctl, j == 0, ctx->stream);
+                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[3 * j], ctx->stream));
+                launch_discharge(S.G, false, S.g, sj, o.gr_beta, sink, dgrid, ctx->stream);
+                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[3 * j + 1], ctx->stream));
+                launch_merge(S.Gm, false, S.g, sj, sink, other, mgrid, ctx->stream);
+                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[3 * j + 2], ctx->stream));
+                launch_round_close(ctx->ctl, j == 0, W, o.gr_round_charge, o.gr_freq_num, o.gr_freq_den,
+                                   o.gr_alpha * n + m, S.dense_threshold, ctx->stream);
+                std::swap(sj.A, sj.A2);
+            }
+            mf_status st = read_ctl(ctx);
+            if (st != MF_OK) return st;
+            const Ctl &c = *ctx->ctl_host;
+            const int r = c.batch_rounds;
+            const bool stopped = c.batch_stop != 0;
+            W = c.batch_W;
+            ps.rounds += r;
+            if ((stopped ? r - 1 : r) & 1) std::swap(S.st.A, S.st.A2);   // rounds the device closed
+            if (S.profile) {
+                const int64_t p = c.pushes - S.last.pushes;
+                int64_t bd = 40 * (c.dverts - S.last.dverts) + 13 * (c.dslots - S.last.dslots) + 16 * p;
+                int64_t bm = 41 * (c.mverts - S.last.mverts) + 4 * (c.mslots - S.last.mslots) + 12 * p;
+                for (int j = 0; j < K; j++) {
+                    const double md = elapsed(ctx->lev[3 * j], ctx->lev[3 * j + 1]);
+                    const double mm = elapsed(ctx->lev[3 * j + 1], ctx->lev[3 * j + 2]);
+                    kernel_record(S, MF_K_DISCHARGE_LIST, md, bd);
+                    kernel_record(S, MF_K_MERGE_LIST, mm, bm);
+                    bd = bm = 0;
+                    S.ms_dis += md;
+                    S.ms_mer += mm;
+                }
+                S.n_dis += K;
+                S.n_mer += K;
+                S.last = c;
+            }
+            if (!stopped) {
+                list_ready = true;
+                na = c.na;
+                rbatch = std::min(16, 2 * rbatch);
+                continue;
+            }
+            // the round that stopped the batch: its merge listed the next
+            // working set in A2
+            const int count = c.na2;
+            dense = count > S.dense_threshold;
+            launch_round_end(ctx->ctl, ctx->stream);   // na = na2
+            std::swap(S.st.A, S.st.A2);
+            list_ready = true;
+            na = count;
+            continue;
         }
-        const int64_t cand_items = dense ? n : (int64_t)na * (1 + S.avg_deg_ceil);
-        launch_merge(S.Gm, dense, S.g, S.st, sink, other, grid_for(cand_items, 256 / S.Gm, S.maxgrid),
-                     ctx->stream);
+        // Dense round: the working set as a list (the previous round's merge
+        // wrote it; after a global relabel it is listed from the activity
+        // flags), discharge the listed vertices, list the touched vertices,
+        // merge them.
+        rbatch = 1;
+        launch_round_reset(ctx->ctl, !list_ready, ctx->stream);
+        const int groups = 256 / S.G;
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[0], ctx->stream));
+        if (!list_ready) launch_compact_flags(S.st.act, (int)n, S.st.A, &ctx->ctl->na, S.maxgrid, ctx->stream);
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[1], ctx->stream));
+        launch_discharge(S.G, true, S.g, S.st, o.gr_beta, sink, grid_for(na, groups, S.maxgrid), ctx->stream);
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[2], ctx->stream));
+        launch_compact_flags(S.st.touched, (int)n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream);
         if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[3], ctx->stream));
+        const int64_t cand_items = std::min<int64_t>(n, (int64_t)na * (1 + S.avg_deg_ceil));
+        launch_merge(S.Gm, true, S.g, S.st, sink, other, grid_for(cand_items, 256 / S.Gm, S.maxgrid),
+                     ctx->stream);
+        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
         if (S.profile) {
-            const double md = elapsed(ctx->pev[0], ctx->pev[1]), mm = elapsed(ctx->pev[2], ctx->pev[3]);
+            const double c1 = elapsed(ctx->pev[0], ctx->pev[1]), md = elapsed(ctx->pev[1], ctx->pev[2]);
+            const double c2 = elapsed(ctx->pev[2], ctx->pev[3]), mm = elapsed(ctx->pev[3], ctx->pev[4]);
             S.ms_dis += md;
             S.ms_mer += mm;
             S.n_dis++;
             S.n_mer++;
             const Ctl &c = *ctx->ctl_host;
             const int64_t p = c.pushes - S.last.pushes;
-            const int64_t flags = dense ? n : 0;
-            kernel_record(S, dense ? MF_K_DISCHARGE_DENSE : MF_K_DISCHARGE_LIST, md,
-                          40 * (c.dverts - S.last.dverts) + 13 * (c.dslots - S.last.dslots) + 16 * p + flags);
-            kernel_record(S, dense ? MF_K_MERGE_DENSE : MF_K_MERGE_LIST, mm,
-                          41 * (c.mverts - S.last.mverts) + 4 * (c.mslots - S.last.mslots) + 12 * p + flags);
+            if (!list_ready) kernel_record(S, MF_K_COMPACT, c1, n + 4 * (int64_t)c.na);
+            kernel_record(S, MF_K_DISCHARGE_DENSE, md,
+                          40 * (c.dverts - S.last.dverts) + 13 * (c.dslots - S.last.dslots) + 16 * p);
+            kernel_record(S, MF_K_COMPACT, c2, n + 4 * (int64_t)c.nc);
+            kernel_record(S, MF_K_MERGE_DENSE, mm,
+                          41 * (c.mverts - S.last.mverts) + 4 * (c.mslots - S.last.mslots) + 12 * p);
             S.last = c;
         }
-        if (dense) S.dense_rounds++;
+        S.dense_rounds++;
         W += ctx->ctl_host->work + o.gr_round_charge;
         const int count = ctx->ctl_host->na2;
-        const bool was_dense = dense;
-        prepare_working_set(S, count, !was_dense, dense);
-        if (!was_dense && !dense) {
-            launch_round_end(ctx->ctl, ctx->stream);   // na = na2
-            std::swap(S.st.A, S.st.A2);
-        }
+        dense = count > S.dense_threshold;
+        launch_round_end(ctx->ctl, ctx->stream);   // the merge listed the next working set: na = na2
+        std::swap(S.st.A, S.st.A2);
+        list_ready = true;
         na = count;
         ps.rounds++;
     }
@@ -657,7 +761,7 @@ static mf_status run_phase_persistent(Solve &S, int sink, int other, int64_t max
     P.max_rounds = max_rounds;
     P.dense_threshold = S.dense_threshold;
     P.bu_factor = S.bu_factor;
-    P.hubdeg = S.hubdeg;
+    P.hubdeg = 64 * S.G;          // the phase kernel expands frontier vertices with G lanes
     P.limit_ticks = ctx->wall_hz * 30ull;      // 30 s: far above any single step
     int per_cu = phase_blocks_per_cu(S.G);
     if (per_cu <= 0) return fail(ctx, MF_EDEVICE, "occupancy query for the persistent kernel failed");
@@ -711,7 +815,7 @@ static mf_status check_options(mf_context *ctx, const mf_options *o)
         o->gr_round_charge < 0 || o->max_rounds < 0)
         return fail(ctx, MF_EINVAL, "invalid global-relabel schedule");
     if (o->lanes_per_vertex < 0 || o->lanes_per_vertex > 64 || o->lanes_per_merge < 0 ||
-        o->lanes_per_merge > 64)
+        o->lanes_per_merge > 64 || o->lanes_per_bfs < 0 || o->lanes_per_bfs > 64)
         return fail(ctx, MF_EINVAL, "lane counts must be 0..64");
     return MF_OK;
 }
@@ -755,13 +859,18 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.st.Q2 = w.Q2;
     S.st.ctl = ctx->ctl;
     S.opt = o;
-    S.G = pick_lanes(o.lanes_per_vertex, dg->n, dg->slots);
+    {
+        int Ga = 4, Gba = 8;
+        auto_lanes(dg, Ga, Gba);
+        S.G = o.lanes_per_vertex > 0 ? pick_lanes(o.lanes_per_vertex, 1, 1) : Ga;
+        S.Gb = o.lanes_per_bfs > 0 ? pick_lanes(o.lanes_per_bfs, 1, 1) : Gba;
+    }
     S.Gm = o.lanes_per_merge > 0 ? pick_lanes(o.lanes_per_merge, 1, 1) : S.G;
     S.maxgrid = ctx->num_cus * 16;
     S.avg_deg_ceil = (dg->slots + dg->n - 1) / std::max<int64_t>(1, dg->n);
     S.dense_threshold = std::min<int64_t>(65536, std::max<int64_t>(2048, dg->n / 512));
     S.bu_factor = 8;
-    S.hubdeg = 64 * S.G;
+    S.hubdeg = 64 * S.Gb;
     S.profile = (o.flags & MF_PROFILE) != 0;
     S.persistent = (o.flags & MF_PERSISTENT) != 0;
     if (o.dense_threshold > 0) S.dense_threshold = o.dense_threshold;
@@ -771,6 +880,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     HIPCHK(ctx, hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
     launch_init_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
     launch_saturate(S.g, S.st, ctx->num_cus * 4, ctx->stream);
+    launch_compact_flags(S.st.touched, n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream);
     launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, grid_for(n, 256 / S.Gm, S.maxgrid), ctx->stream);
 
     PhaseStats p1;
