@@ -100,7 +100,11 @@ typedef struct {
     int32_t blocks_per_cu;       /* persistent kernel blocks per compute unit: 0 = occupancy limit */
     int32_t lanes_per_bfs;       /* lanes that expand one frontier vertex in a top-down BFS level of
                                     the global relabel: 0 = automatic, else 1..64, power of 2 */
-    int32_t reserved[2];
+    uint32_t profile_mask;       /* with MF_PROFILE: kernels (bit k = mf_kernel_id k) whose launches are
+                                    timed with HIP events; 0 = all.  Events cost device time, so a
+                                    caller timing a solve restricts them to the kernel it studies;
+                                    bytes and launch counts are kept for every kernel */
+    int32_t reserved[1];
 } mf_options;
 
 typedef struct {
@@ -137,6 +141,8 @@ typedef struct {
  *     vertex, 12 per push received;
  *   flag compaction (dense rounds list their working set and their touched
  *     vertices): n per pass plus 4 per listed vertex;
+ *   hub discharge / hub merge (a block per vertex of degree above 64 lanes
+ *     per vertex): as discharge / merge, for the hub vertices;
  *   top-down level: 12 per frontier vertex, 12 per slot examined, 8 per
  *     vertex labelled;  hub expansion: 12 per hub, 12 per slot examined;
  *   bottom-up level: 4 per vertex, 8 per unlabelled vertex, 12 per slot
@@ -150,7 +156,9 @@ typedef enum {
     MF_K_GR_HUB = 5,
     MF_K_GR_BOTTOMUP = 6,
     MF_K_COMPACT = 7,
-    MF_K_COUNT = 8
+    MF_K_DISCHARGE_HUB = 8,
+    MF_K_MERGE_HUB = 9,
+    MF_K_COUNT = 10
 } mf_kernel_id;
 
 typedef struct mf_context mf_context;

@@ -44,7 +44,7 @@ class mf_options(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("lanes_per_vertex", ctypes.c_int32),
                 ("lanes_per_merge", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_bfs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("profile_mask", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class mf_stats(ctypes.Structure):
@@ -62,7 +62,7 @@ class mf_stats(ctypes.Structure):
 
 # kernel names of mf_stats.kernel_* in index order (mf_kernel_id)
 KERNEL_NAMES = ("k_discharge_list", "k_discharge_dense", "k_merge_list", "k_merge_dense", "k_gr_td",
-                "k_gr_hub", "k_gr_bu", "k_compact_flags")
+                "k_gr_hub", "k_gr_bu", "k_compact_flags", "k_discharge_hubs", "k_merge_hubs")
 
 
 class mf_result(ctypes.Structure):

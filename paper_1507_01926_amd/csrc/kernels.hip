@@ -17,7 +17,10 @@
 //                and decides whether w is active in the next round.
 // A global relabel (Sec. 2.1, Sec. 3) is a level-synchronous reverse BFS from
 // the sink (k_gr_init, k_gr_level per level, k_gr_rebuild).
+#include <hip/hip_ext.h>
+
 #include "mf_device.h"
+#include "mf_phase.h"
 #include "mf_steps.h"
 
 namespace mf {
@@ -342,8 +345,14 @@ __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView s
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
     DisAcc acc;
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups)
-        discharge_vertex<G, false>(g, st, p, st.A[i], gl, acc);
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups) {
+        const int v = st.A[i];
+        if (g.off[v + 1] - g.off[v] > p.hubd) {        // left to k_discharge_hubs
+            wave_append(gl == 0, v, st.H, &st.ctl->nhd);
+            continue;
+        }
+        discharge_vertex<G, false>(g, st, p, v, gl, acc);
+    }
     discharge_flush(st, p, acc);
 }
 
@@ -359,8 +368,14 @@ __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView 
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
     DisAcc acc;
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups)
-        discharge_vertex<G, true>(g, st, p, st.A[i], gl, acc);
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups) {
+        const int v = st.A[i];
+        if (g.off[v + 1] - g.off[v] > p.hubd) {        // left to k_discharge_hubs
+            wave_append(gl == 0, v, st.H, &st.ctl->nhd);
+            continue;
+        }
+        discharge_vertex<G, true>(g, st, p, v, gl, acc);
+    }
     discharge_flush(st, p, acc);
 }
 
@@ -372,7 +387,7 @@ __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView 
 // over all vertices.
 
 template <int G>
-__global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, int sink, int other)
+__global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, int sink, int other, int hubd)
 {
     if (st.ctl->batch_stop) return;
     const int nc = st.ctl->nc;
@@ -384,6 +399,10 @@ __global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, i
     for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups) {
         const int w = st.C[i];
         if (st.owner[w] != i) continue;
+        if (g.off[w + 1] - g.off[w] > hubd) {           // left to k_merge_hubs
+            wave_append(gl == 0, w, st.H, &st.ctl->nhm);
+            continue;
+        }
         merge_vertex<G, false>(g, st, w, gl, sink, other, acc, &stage);
     }
     stage_flush(stage, st.A2, &st.ctl->na2);
@@ -392,7 +411,7 @@ __global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, i
 
 // Dense mode: the touched vertices, listed in C[0 .. nc) by k_compact_flags.
 template <int G>
-__global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, int sink, int other)
+__global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, int sink, int other, int hubd)
 {
     const int nc = st.ctl->nc;
     const int gl = threadIdx.x & (G - 1);
@@ -400,8 +419,14 @@ __global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, 
     MerAcc acc;
     MF_STAGE(stage);
     stage_init(stage);
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups)
-        merge_vertex<G, true>(g, st, st.C[i], gl, sink, other, acc, &stage);
+    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nc; i += gridDim.x * groups) {
+        const int w = st.C[i];
+        if (g.off[w + 1] - g.off[w] > hubd) {           // left to k_merge_hubs
+            wave_append(gl == 0, w, st.H, &st.ctl->nhm);
+            continue;
+        }
+        merge_vertex<G, true>(g, st, w, gl, sink, other, acc, &stage);
+    }
     stage_flush(stage, st.A2, &st.ctl->na2);
     merge_flush(st, true, acc);
 }
@@ -463,12 +488,44 @@ __global__ __launch_bounds__(256) void k_compact_flags(const uint8_t *__restrict
     }
 }
 
+// Hub vertices of the round, one block each (the vertices the discharge or
+// merge kernels above left in H).
+template <bool DENSE>
+__global__ __launch_bounds__(256) void k_discharge_hubs(GraphView g, StateView st, RoundParams p)
+{
+    if (st.ctl->batch_stop) return;
+    const int nh = st.ctl->nhd;
+    if ((int)blockIdx.x >= nh) return;               // no hub for this block
+    __shared__ int64_t sh64[HUB_BLOCK / 64];
+    __shared__ int sh32[HUB_BLOCK / 64];
+    DisAcc acc;
+    for (int i = blockIdx.x; i < nh; i += gridDim.x) discharge_hub<DENSE>(g, st, p, st.H[i], acc, sh64, sh32);
+    discharge_flush_hub(st, p, acc);
+}
+
+template <bool DENSE>
+__global__ __launch_bounds__(256) void k_merge_hubs(GraphView g, StateView st, int sink, int other)
+{
+    if (st.ctl->batch_stop) return;
+    const int nh = st.ctl->nhm;
+    if ((int)blockIdx.x >= nh) return;               // no hub for this block
+    __shared__ int64_t sh64[HUB_BLOCK / 64];
+    MF_STAGE(stage);
+    stage_init(stage);
+    MerAcc acc;
+    for (int i = blockIdx.x; i < nh; i += gridDim.x) merge_hub<DENSE>(g, st, st.H[i], sink, other, acc, stage, sh64);
+    stage_flush(stage, st.A2, &st.ctl->na2);
+    merge_flush_hub(st, acc);
+}
+
 __global__ void k_round_reset(Ctl *ctl, int dense)
 {
     ctl->nc = 0;
     ctl->na2 = 0;
     ctl->work = 0;
     ctl->batch_stop = 0;
+    ctl->nhd = 0;
+    ctl->nhm = 0;
     if (dense) ctl->na = 0;        // the dense round lists its working set again
 }
 
@@ -479,13 +536,14 @@ __global__ void k_round_end(Ctl *ctl)
 }
 
 // Speculative list rounds: the host launches several rounds of list mode
-// without reading the counters in between.  k_round_begin opens a round
-// (the first one of the batch clears the stop flag and the round count);
+// without reading the counters in between.  k_round_begin opens the first
+// round of a batch (and clears the stop flag and the round count);
 // k_round_close adds the round's relabel work and charge to W and stops the
 // batch when the next round must not run as a list round: its working set
 // is empty or above the dense threshold, or W calls for a global relabel
 // (the conditions the host checks after a single round).  A round that does
-// not stop the batch makes the next working set current (na := na2).
+// not stop the batch makes the next working set current (na := na2) and
+// opens the next round.
 __global__ void k_round_begin(Ctl *ctl, int first)
 {
     if (first) {
@@ -497,6 +555,8 @@ __global__ void k_round_begin(Ctl *ctl, int first)
     ctl->nc = 0;
     ctl->na2 = 0;
     ctl->work = 0;
+    ctl->nhd = 0;
+    ctl->nhm = 0;
 }
 
 __global__ void k_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num,
@@ -512,6 +572,12 @@ __global__ void k_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, i
         return;
     }
     ctl->na = ctl->na2;
+    // open the next round (what k_round_begin does)
+    ctl->nc = 0;
+    ctl->na2 = 0;
+    ctl->work = 0;
+    ctl->nhd = 0;
+    ctl->nhm = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -556,55 +622,78 @@ __global__ void k_read_value(const int64_t *e, int t, Ctl *ctl) { ctl->value = e
     default: CALL(64); break;                     \
     }
 
-void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid,
-                      hipStream_t s)
+// A launch whose events are set records them from the kernel's dispatch (the
+// timestamps of the kernel's own execution).
+#define MF_LAUNCH(K, GRID, S, EV, ...)                                                                \
+    do {                                                                                              \
+        if ((EV).a) hipExtLaunchKernelGGL(K, dim3(GRID), dim3(256), 0, S, (EV).a, (EV).b, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(K, dim3(GRID), dim3(256), 0, S, __VA_ARGS__);                         \
+    } while (0)
+
+void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int hubd, int grid,
+                      hipStream_t s, KEv ev)
 {
-    RoundParams p{beta, sink};
-#define C_(X)                                                                                   \
-    if (dense) hipLaunchKernelGGL((k_discharge_dense<X>), dim3(grid), dim3(256), 0, s, g, st, p); \
-    else hipLaunchKernelGGL((k_discharge_list<X>), dim3(grid), dim3(256), 0, s, g, st, p)
+    RoundParams p{beta, sink, hubd};
+#define C_(X)                                                      \
+    if (dense) MF_LAUNCH((k_discharge_dense<X>), grid, s, ev, g, st, p); \
+    else MF_LAUNCH((k_discharge_list<X>), grid, s, ev, g, st, p)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }
 
-void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int grid,
-                  hipStream_t s)
+void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int hubd, int grid,
+                  hipStream_t s, KEv ev)
 {
-#define C_(X)                                                                                        \
-    if (dense) hipLaunchKernelGGL((k_merge_dense<X>), dim3(grid), dim3(256), 0, s, g, st, sink, other); \
-    else hipLaunchKernelGGL((k_merge_list<X>), dim3(grid), dim3(256), 0, s, g, st, sink, other)
+#define C_(X)                                                                     \
+    if (dense) MF_LAUNCH((k_merge_dense<X>), grid, s, ev, g, st, sink, other, hubd); \
+    else MF_LAUNCH((k_merge_list<X>), grid, s, ev, g, st, sink, other, hubd)
     MF_DISPATCH_G(G, C_)
 #undef C_
+}
+
+void launch_discharge_hubs(bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid, hipStream_t s,
+                           KEv ev)
+{
+    RoundParams p{beta, sink};
+    if (dense) MF_LAUNCH(k_discharge_hubs<true>, grid, s, ev, g, st, p);
+    else MF_LAUNCH(k_discharge_hubs<false>, grid, s, ev, g, st, p);
+}
+
+void launch_merge_hubs(bool dense, GraphView g, StateView st, int sink, int other, int grid, hipStream_t s, KEv ev)
+{
+    if (dense) MF_LAUNCH(k_merge_hubs<true>, grid, s, ev, g, st, sink, other);
+    else MF_LAUNCH(k_merge_hubs<false>, grid, s, ev, g, st, sink, other);
 }
 
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
-                  int32_t *qout, int hubdeg, int grid, hipStream_t s)
+                  int32_t *qout, int hubdeg, int grid, hipStream_t s, KEv ev)
 {
-#define C_(X) hipLaunchKernelGGL((k_gr_td<X>), dim3(grid), dim3(256), 0, s, g, st, level, sink, other, qin, qout, hubdeg)
+#define C_(X) MF_LAUNCH((k_gr_td<X>), grid, s, ev, g, st, level, sink, other, qin, qout, hubdeg)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }
 
 void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int grid,
-                   hipStream_t s)
+                   hipStream_t s, KEv ev)
 {
-    hipLaunchKernelGGL(k_gr_hub, dim3(grid), dim3(256), 0, s, g, st, level, sink, other, qout);
+    MF_LAUNCH(k_gr_hub, grid, s, ev, g, st, level, sink, other, qout);
 }
-void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s)
+void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s, KEv ev)
 {
-    hipLaunchKernelGGL(k_gr_bu, dim3(grid), dim3(256), 0, s, g, st, level, sink, other);
+    MF_LAUNCH(k_gr_bu, grid, s, ev, g, st, level, sink, other);
 }
 void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gr_collect, dim3(grid), dim3(256), 0, s, g, st, level, qout);
 }
-void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s)
+void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s,
+                          KEv ev)
 {
     const int chunks = (n + 15) / 16;
     int grid = (chunks + 255) / 256;
     if (grid > maxgrid) grid = maxgrid;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_compact_flags, dim3(grid), dim3(256), 0, s, flags, n, list, count);
+    MF_LAUNCH(k_compact_flags, grid, s, ev, flags, n, list, count);
 }
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s)

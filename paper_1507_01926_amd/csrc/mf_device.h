@@ -43,6 +43,10 @@ struct Ctl {
     // flag (set by the round that ends the batch) and the relabel work W
     int32_t batch_rounds, batch_stop;
     int64_t batch_W;
+    // hub vertices of a round (discharged / merged by a block each) and
+    // the counters of the hub kernels
+    int32_t nhd, nhm;
+    int64_t dh_verts, dh_slots, dh_pushes, mh_verts, mh_slots;
 };
 
 // Per-solve state.  Every array lives in device memory.

@@ -6,6 +6,14 @@
 #include "mf_device.h"
 
 namespace mf {
+// Events that a timed launch records from its own dispatch (start and end
+// of the kernel's execution); null = untimed.
+struct KEv {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+}  // namespace mf
+
+namespace mf {
 
 // Grid barrier state: arrivals and the generation that waiting blocks poll
 // sit on separate 128-byte lines.

@@ -8,6 +8,7 @@ namespace mf {
 struct RoundParams {
     int64_t beta;      // work per relabel = outdeg + beta
     int sink;          // pushes into the sink go straight to its reverse slot and excess
+    int hubd = 0x7fffffff;   // vertices of higher degree are left to a block each (hub kernels)
 };
 
 // One pass over a chunk of up to G slots, in slot order.  Each lane holds one
@@ -214,6 +215,205 @@ __device__ __forceinline__ void merge_flush(StateView &st, bool dense, MerAcc &a
     (void)dense;
     block_add64(acc.mverts, &st.ctl->mverts);
     block_add64(acc.mslots, &st.ctl->mslots);
+}
+
+// ---------------------------------------------------------------------------
+// Hub vertices: one block of 256 threads discharges (or merges) one vertex of
+// very high degree, 256 slots at a time.  The block reproduces the group
+// version exactly: the in-order push is a block prefix sum of the usable
+// residuals clamped to the excess, the relabel candidate a block minimum and
+// "skipped" a block OR, over the chunks a pass scans.
+
+constexpr int HUB_BLOCK = 256;
+
+// Inclusive prefix sum over the block; *total receives the block sum.  All
+// threads must call it.  sh: LDS [HUB_BLOCK / 64].
+__device__ __forceinline__ int64_t block_incl_scan64(int64_t x, int64_t &total, int64_t *sh)
+{
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, (unsigned)o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < HUB_BLOCK / 64; k++) {
+        const int64_t t = sh[k];
+        if (k < wv) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return x + off;
+}
+
+__device__ __forceinline__ int block_min32(int x, int *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const int y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    if (lane_id() == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int m = sh[0];
+#pragma unroll
+    for (int k = 1; k < HUB_BLOCK / 64; k++) m = sh[k] < m ? sh[k] : m;
+    __syncthreads();
+    return m;
+}
+
+__device__ __forceinline__ int block_or32(int x, int *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+    if (lane_id() == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < HUB_BLOCK / 64; k++) m |= sh[k];
+    __syncthreads();
+    return m;
+}
+
+template <bool DENSE>
+__device__ __forceinline__ void discharge_hub(const GraphView &g, StateView &st, const RoundParams &p, int v,
+                                              DisAcc &acc, int64_t *sh64, int *sh32)
+{
+    const int n = g.n;
+    const int beg = g.off[v], end = g.off[v + 1], deg = end - beg;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        acc.dverts++;
+        acc.dslots += deg;
+    }
+    const int dv = st.d[v];
+    int dp = dv;
+    int64_t el = st.e[v];
+    while (el > 0) {
+        int cand = n;
+        int sk = 0;
+        for (int base = beg; base < end; base += HUB_BLOCK) {
+            const int a = base + tid;
+            int r = 0, w = -1, dw = 0;
+            bool aw = false;
+            if (a < end) {
+                r = st.res[a];
+                if (r > 0) {
+                    w = g.head[a];
+                    dw = st.d[w];
+                    aw = st.act[w] != 0;
+                }
+            }
+            if (tid == 0) acc.scans += (end - base) < HUB_BLOCK ? (end - base) : HUB_BLOCK;
+            const bool adm = r > 0 && dp == dw + 1;
+            const bool win = (dv == dw + 1) || (dv < dw - 1) || (dv == dw && v < w);
+            const bool lose = adm && aw && !win;
+            const bool use = adm && !lose;
+            const int64_t amt = use ? (int64_t)r : 0;
+            int64_t tot;
+            const int64_t incl = block_incl_scan64(amt, tot, sh64);
+            const int64_t excl = incl - amt;
+            int dl = 0;
+            if (use && excl < el) {
+                const int64_t rem = el - excl;
+                dl = rem < (int64_t)r ? (int)rem : r;
+            }
+            const bool into_sink = w == p.sink;
+            if (dl > 0) {
+                r -= dl;
+                acc.pushes++;
+                if (into_sink) {
+                    st.res[g.rev[a]] += dl;
+                    acc.to_sink += dl;
+                } else {
+                    st.delta[g.rev[a]] = dl;
+                    if (DENSE) st.touched[w] = 1;
+                }
+                st.res[a] = r;
+            }
+            if (!DENSE) {
+                const bool app = dl > 0 && !into_sink;
+                const int idx = wave_append(app, w, st.C, &st.ctl->nc);
+                if (app) st.owner[w] = idx;
+            }
+            el = tot >= el ? 0 : el - tot;
+            if (el == 0) break;
+            if (r > 0 && dw >= dp && dw + 1 < cand) cand = dw + 1;
+            sk |= lose ? 1 : 0;
+        }
+        if (el == 0) break;
+        const int nl = block_min32(cand, sh32);
+        if (block_or32(sk, sh32)) break;
+        dp = nl < n ? nl : n;
+        if (tid == 0) {
+            acc.work += deg + p.beta;
+            acc.relabels++;
+        }
+        if (dp >= n) break;
+    }
+    if (tid == 0) {
+        st.dn[v] = dp;
+        st.e[v] = el;
+        if (DENSE) st.touched[v] = 1;
+    }
+    if (!DENSE) {
+        const int idx = wave_append(tid == 0, v, st.C, &st.ctl->nc);
+        if (tid == 0) st.owner[v] = idx;
+    }
+}
+
+__device__ __forceinline__ void discharge_flush_hub(StateView &st, const RoundParams &p, DisAcc &acc)
+{
+    block_add64(acc.to_sink, &st.e[p.sink]);
+    block_add64(acc.work, &st.ctl->work);
+    block_add64(acc.pushes, &st.ctl->pushes);
+    block_add64(acc.pushes, &st.ctl->dh_pushes);
+    block_add64(acc.relabels, &st.ctl->relabels);
+    block_add64(acc.scans, &st.ctl->scans);
+    block_add64(acc.dverts, &st.ctl->dh_verts);
+    block_add64(acc.dslots, &st.ctl->dh_slots);
+}
+
+__device__ __forceinline__ void merge_flush_hub(StateView &st, MerAcc &acc)
+{
+    block_add64(acc.mverts, &st.ctl->mh_verts);
+    block_add64(acc.mslots, &st.ctl->mh_slots);
+}
+
+template <bool DENSE>
+__device__ __forceinline__ void merge_hub(const GraphView &g, StateView &st, int w, int sink, int other,
+                                          MerAcc &acc, Stage &sg, int64_t *sh64)
+{
+    const int beg = g.off[w], end = g.off[w + 1];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        acc.mverts++;
+        acc.mslots += end - beg;
+    }
+    int64_t sum = 0;
+    for (int a = beg + tid; a < end; a += HUB_BLOCK) {
+        const int dl = st.delta[a];
+        if (dl != 0) {
+            st.res[a] += dl;
+            st.delta[a] = 0;
+            sum += dl;
+        }
+    }
+    int64_t tot;
+    (void)block_incl_scan64(sum, tot, sh64);
+    bool pa = false;
+    if (tid == 0) {
+        const int64_t e = st.e[w] + tot;
+        st.e[w] = e;
+        const int dnew = st.dn[w];
+        st.d[w] = dnew;
+        pa = w != sink && w != other && e > 0 && dnew < g.n;
+        st.act[w] = pa;
+        if (DENSE) st.touched[w] = 0;
+    }
+    stage_append(sg, pa, w, st.A2, &st.ctl->na2);
 }
 
 }  // namespace mf

@@ -29,17 +29,23 @@
 #include "mf_host.h"
 
 namespace mf {
-void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid,
-                      hipStream_t s);
-void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int grid,
-                  hipStream_t s);
+void launch_discharge_hubs(bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid, hipStream_t s,
+                           KEv ev = KEv());
+void launch_merge_hubs(bool dense, GraphView g, StateView st, int sink, int other, int grid, hipStream_t s,
+                       KEv ev = KEv());
+void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int hubd, int grid,
+                      hipStream_t s, KEv ev = KEv());
+void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int hubd, int grid,
+                  hipStream_t s, KEv ev = KEv());
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
-                  int32_t *qout, int hubdeg, int grid, hipStream_t s);
+                  int32_t *qout, int hubdeg, int grid, hipStream_t s, KEv ev = KEv());
 void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int grid,
-                   hipStream_t s);
-void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s);
+                   hipStream_t s, KEv ev = KEv());
+void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s,
+                  KEv ev = KEv());
 void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s);
-void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s);
+void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s,
+                          KEv ev = KEv());
 void launch_degree_stats(GraphView g, Ctl *ctl, int grid, hipStream_t s);
 void launch_round_begin(Ctl *ctl, int first, hipStream_t s);
 void launch_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num, int64_t freq_den,
@@ -84,6 +90,7 @@ void mf_options_default(mf_options *o)
     o->lanes_per_vertex = 0;
     o->lanes_per_merge = 0;
     o->lanes_per_bfs = 0;
+    o->profile_mask = 0;
 }
 
 const char *mf_version(void) { return "mi355x-maxflow 0.1 (gfx950)"; }
@@ -403,12 +410,16 @@ struct Solve {
     StateView st;
     mf_options opt;
     int G, Gm, Gb;             // lanes per vertex: discharge, merge, top-down BFS level
+    int hubd;                  // round vertices above this degree go to the hub kernels (a block each)
+    bool hub_kernels;          // some vertex other than s and t exceeds hubd
+    int hub_grid;
     int maxgrid;
     int64_t avg_deg_ceil;
     int64_t dense_threshold;   // working sets larger than this run in dense mode
     int64_t bu_factor;         // bottom-up BFS level when frontier * bu_factor > unvisited
     int hubdeg;                // frontier vertices above this degree are expanded by the grid
     bool profile;
+    uint32_t pmask;            // kernels (bits of mf_kernel_id) timed with events under MF_PROFILE
     bool persistent;
     // profiling accumulators
     double ms_dis = 0, ms_mer = 0, ms_gr = 0, ms_phase = 0;
@@ -426,11 +437,44 @@ static void kernel_record(Solve &S, int k, double ms, int64_t bytes)
     S.kb[k] += bytes;
 }
 
+// Algorithmic bytes of the rounds since the last readback: discharge, hub
+// discharge, merge, hub merge (the per-unit model of mf_kernel_id).
+static void round_bytes(const Solve &S, const Ctl &c, int64_t b[4])
+{
+    const Ctl &l = S.last;
+    const int64_t p = c.pushes - l.pushes, ph = c.dh_pushes - l.dh_pushes;
+    b[0] = 40 * (c.dverts - l.dverts) + 13 * (c.dslots - l.dslots) + 16 * (p - ph);
+    b[1] = 40 * (c.dh_verts - l.dh_verts) + 13 * (c.dh_slots - l.dh_slots) + 16 * ph;
+    b[2] = 41 * (c.mverts - l.mverts) + 4 * (c.mslots - l.mslots) + 12 * p;
+    b[3] = 41 * (c.mh_verts - l.mh_verts) + 4 * (c.mh_slots - l.mh_slots);
+}
+
 static float elapsed(hipEvent_t a, hipEvent_t b)
 {
     float ms = 0;
     (void)hipEventElapsedTime(&ms, a, b);
     return ms;
+}
+
+// With MF_PROFILE, launches of the kernels in the profile mask are bracketed
+// by HIP events (an event costs device time, so a caller that times a solve
+// can restrict them to the kernel it studies); bytes and launch counts are
+// kept for every kernel.
+static bool timed(const Solve &S, int kind) { return S.profile && ((S.pmask >> kind) & 1u); }
+// ev: an event array (read only when the kernel is timed); the launch records
+// ev[i] and ev[i+1] from its own dispatch.
+static KEv kev(const Solve &S, int kind, const hipEvent_t *ev, int i)
+{
+    KEv k;
+    if (timed(S, kind)) {
+        k.a = ev[i];
+        k.b = ev[i + 1];
+    }
+    return k;
+}
+static double span(const Solve &S, int kind, const hipEvent_t *ev, int a, int b)
+{
+    return timed(S, kind) ? (double)elapsed(ev[a], ev[b]) : 0.0;
 }
 
 // Working-set representation for the next round: a list for small sets, the
@@ -485,22 +529,23 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             // levels after the one that empties the frontier return at once.
             const int K = batch;
             const int grid = grid_for(K == 1 ? nq : std::max<int64_t>(4 * nq, 2048), groups, S.maxgrid);
-            int nl = 0;                // launches, with their kinds for the profile
+            // launches, with their kinds for the profile; events lev[2i] and
+            // lev[2i+1] bracket launch i
+            int nl = 0;
             int kinds[2 * 32];
             if (S.profile) {
-                mf_status est = batch_events(ctx, 2 * 32 + 1);
+                mf_status est = batch_events(ctx, 4 * 32);
                 if (est != MF_OK) return est;
-                HIPCHK(ctx, hipEventRecord(ctx->lev[0], ctx->stream));
             }
             for (int j = 0; j < K; j++) {
                 const int L = level + j;
-                launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, grid, ctx->stream);
+                launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, grid, ctx->stream,
+                       kev(S, MF_K_GR_TOPDOWN, ctx->lev.data(), 2 * nl));
                 kinds[nl++] = MF_K_GR_TOPDOWN;
-                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[nl], ctx->stream));
                 if (L == 0 ? hub_first : hub_later) {
-                    launch_gr_hub(S.g, S.st, L, sink, other, qout, ctx->num_cus * 2, ctx->stream);
+                    launch_gr_hub(S.g, S.st, L, sink, other, qout, ctx->num_cus * 2, ctx->stream,
+                           kev(S, MF_K_GR_HUB, ctx->lev.data(), 2 * nl));
                     kinds[nl++] = MF_K_GR_HUB;
-                    if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[nl], ctx->stream));
                 }
                 std::swap(qin, qout);
             }
@@ -522,7 +567,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
                     int64_t b = 0;
                     if (k == MF_K_GR_TOPDOWN) { b = td_bytes; td_bytes = 0; }
                     else { b = hub_bytes; hub_bytes = 0; }
-                    const double ms = elapsed(ctx->lev[i], ctx->lev[i + 1]);
+                    const double ms = span(S, k, ctx->lev.data(), 2 * i, 2 * i + 1);
                     kernel_record(S, k, ms, b);
                     S.ms_gr += ms;
                 }
@@ -539,42 +584,45 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
         }
         // one level at a time: bottom-up, or top-down after a bottom-up level
         const bool hubs = level == 0 ? hub_first : hub_later;
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
         if (bottom_up) {
             S.bu_levels++;
-            launch_gr_bu(S.g, S.st, level, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream);
+            launch_gr_bu(S.g, S.st, level, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream,
+                   kev(S, MF_K_GR_BOTTOMUP, ctx->pev, 4));
             have_list = false;
         } else {
             S.td_levels++;
             HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
             launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
-            if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
             launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg,
-                         grid_for(nq, groups, S.maxgrid), ctx->stream);
-            if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[6], ctx->stream));
-            if (hubs) launch_gr_hub(S.g, S.st, level, sink, other, qout, ctx->num_cus * 2, ctx->stream);
+                         grid_for(nq, groups, S.maxgrid), ctx->stream,
+                   kev(S, MF_K_GR_TOPDOWN, ctx->pev, 4));
+            if (hubs) {
+                launch_gr_hub(S.g, S.st, level, sink, other, qout, ctx->num_cus * 2, ctx->stream,
+                       kev(S, MF_K_GR_HUB, ctx->pev, 6));
+            }
             std::swap(qin, qout);
             have_list = true;
         }
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[5], ctx->stream));
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
         const Ctl &c = *ctx->ctl_host;
         const int64_t found = c.nq[(level + 1) % 3];
         if (S.profile) {
-            const double ms = elapsed(ctx->pev[4], ctx->pev[5]);
-            S.ms_gr += ms;
             S.n_gr++;
             const int64_t gs = c.gslots - S.last.gslots;
             if (bottom_up) {
+                const double ms = span(S, MF_K_GR_BOTTOMUP, ctx->pev, 4, 5);
+                S.ms_gr += ms;
                 kernel_record(S, MF_K_GR_BOTTOMUP, ms, 4 * (int64_t)n + 8 * unvisited + 12 * gs + 8 * found);
             } else {
-                const double ms_td = elapsed(ctx->pev[4], ctx->pev[6]);
+                const double ms_td = span(S, MF_K_GR_TOPDOWN, ctx->pev, 4, 5);
+                S.ms_gr += ms_td;
                 kernel_record(S, MF_K_GR_TOPDOWN, ms_td, 12 * nq + 12 * gs + 8 * found);
                 if (hubs) {
                     const int64_t nh = c.nh[level % 3];
-                    kernel_record(S, MF_K_GR_HUB, elapsed(ctx->pev[6], ctx->pev[5]),
-                                  12 * nh + 12 * (c.hslots - S.last.hslots));
+                    const double ms_h = span(S, MF_K_GR_HUB, ctx->pev, 6, 7);
+                    S.ms_gr += ms_h;
+                    kernel_record(S, MF_K_GR_HUB, ms_h, 12 * nh + 12 * (c.hslots - S.last.hslots));
                 }
             }
             S.last = c;
@@ -637,17 +685,28 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             const int mgrid = grid_for(std::min<int64_t>(S.dense_threshold, 4 * (int64_t)na + 2048) *
                                            (1 + S.avg_deg_ceil), 256 / S.Gm, S.maxgrid);
             if (S.profile) {
-                mf_status est = batch_events(ctx, 3 * 16);
+                mf_status est = batch_events(ctx, 8 * 16);
                 if (est != MF_OK) return est;
             }
+            // events 8j .. 8j+7 bracket the discharge, hub discharge, merge and
+            // hub merge of round j (the hub pairs stay empty without hubs)
             StateView sj = S.st;
             for (int j = 0; j < K; j++) {
-                launch_round_begin(ctx->ctl, j == 0, ctx->stream);
-                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[3 * j], ctx->stream));
-                launch_discharge(S.G, false, S.g, sj, o.gr_beta, sink, dgrid, ctx->stream);
-                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[3 * j + 1], ctx->stream));
-                launch_merge(S.Gm, false, S.g, sj, sink, other, mgrid, ctx->stream);
-                if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->lev[3 * j + 2], ctx->stream));
+                const hipEvent_t *e = ctx->lev.data();
+                const int q = 8 * j;
+                if (j == 0) launch_round_begin(ctx->ctl, 1, ctx->stream);
+                launch_discharge(S.G, false, S.g, sj, o.gr_beta, sink, S.hubd, dgrid, ctx->stream,
+                       kev(S, MF_K_DISCHARGE_LIST, e, q + 0));
+                if (S.hub_kernels) {
+                    launch_discharge_hubs(false, S.g, sj, o.gr_beta, sink, S.hub_grid, ctx->stream,
+                           kev(S, MF_K_DISCHARGE_HUB, e, q + 2));
+                }
+                launch_merge(S.Gm, false, S.g, sj, sink, other, S.hubd, mgrid, ctx->stream,
+                       kev(S, MF_K_MERGE_LIST, e, q + 4));
+                if (S.hub_kernels) {
+                    launch_merge_hubs(false, S.g, sj, sink, other, S.hub_grid, ctx->stream,
+                           kev(S, MF_K_MERGE_HUB, e, q + 6));
+                }
                 launch_round_close(ctx->ctl, j == 0, W, o.gr_round_charge, o.gr_freq_num, o.gr_freq_den,
                                    o.gr_alpha * n + m, S.dense_threshold, ctx->stream);
                 std::swap(sj.A, sj.A2);
@@ -661,17 +720,25 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             ps.rounds += r;
             if ((stopped ? r - 1 : r) & 1) std::swap(S.st.A, S.st.A2);   // rounds the device closed
             if (S.profile) {
-                const int64_t p = c.pushes - S.last.pushes;
-                int64_t bd = 40 * (c.dverts - S.last.dverts) + 13 * (c.dslots - S.last.dslots) + 16 * p;
-                int64_t bm = 41 * (c.mverts - S.last.mverts) + 4 * (c.mslots - S.last.mslots) + 12 * p;
+                int64_t b[4];
+                round_bytes(S, c, b);
                 for (int j = 0; j < K; j++) {
-                    const double md = elapsed(ctx->lev[3 * j], ctx->lev[3 * j + 1]);
-                    const double mm = elapsed(ctx->lev[3 * j + 1], ctx->lev[3 * j + 2]);
-                    kernel_record(S, MF_K_DISCHARGE_LIST, md, bd);
-                    kernel_record(S, MF_K_MERGE_LIST, mm, bm);
-                    bd = bm = 0;
+                    const hipEvent_t *e = ctx->lev.data();
+                    const int q = 8 * j;
+                    const double md = span(S, MF_K_DISCHARGE_LIST, e, q, q + 1);
+                    const double mm = span(S, MF_K_MERGE_LIST, e, q + 4, q + 5);
+                    kernel_record(S, MF_K_DISCHARGE_LIST, md, j == 0 ? b[0] : 0);
+                    kernel_record(S, MF_K_MERGE_LIST, mm, j == 0 ? b[2] : 0);
                     S.ms_dis += md;
                     S.ms_mer += mm;
+                    if (S.hub_kernels) {
+                        const double hd = span(S, MF_K_DISCHARGE_HUB, e, q + 2, q + 3);
+                        const double hm = span(S, MF_K_MERGE_HUB, e, q + 6, q + 7);
+                        kernel_record(S, MF_K_DISCHARGE_HUB, hd, j == 0 ? b[1] : 0);
+                        kernel_record(S, MF_K_MERGE_HUB, hm, j == 0 ? b[3] : 0);
+                        S.ms_dis += hd;
+                        S.ms_mer += hm;
+                    }
                 }
                 S.n_dis += K;
                 S.n_mer += K;
@@ -700,34 +767,53 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
         rbatch = 1;
         launch_round_reset(ctx->ctl, !list_ready, ctx->stream);
         const int groups = 256 / S.G;
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[0], ctx->stream));
-        if (!list_ready) launch_compact_flags(S.st.act, (int)n, S.st.A, &ctx->ctl->na, S.maxgrid, ctx->stream);
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[1], ctx->stream));
-        launch_discharge(S.G, true, S.g, S.st, o.gr_beta, sink, grid_for(na, groups, S.maxgrid), ctx->stream);
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[2], ctx->stream));
-        launch_compact_flags(S.st.touched, (int)n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream);
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[3], ctx->stream));
+        if (S.profile) {
+            mf_status est = batch_events(ctx, 12);
+            if (est != MF_OK) return est;
+        }
+        // events bracket: compaction of the working set, discharge, hub
+        // discharge, compaction of the touched vertices, merge, hub merge
+        const hipEvent_t *e = ctx->lev.data();
+        if (!list_ready) {
+            launch_compact_flags(S.st.act, (int)n, S.st.A, &ctx->ctl->na, S.maxgrid, ctx->stream,
+                   kev(S, MF_K_COMPACT, e, 0));
+        }
+        launch_discharge(S.G, true, S.g, S.st, o.gr_beta, sink, S.hubd, grid_for(na, groups, S.maxgrid),
+                         ctx->stream,
+               kev(S, MF_K_DISCHARGE_DENSE, e, 2));
+        if (S.hub_kernels) {
+            launch_discharge_hubs(true, S.g, S.st, o.gr_beta, sink, S.hub_grid, ctx->stream,
+                   kev(S, MF_K_DISCHARGE_HUB, e, 4));
+        }
+        launch_compact_flags(S.st.touched, (int)n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream,
+               kev(S, MF_K_COMPACT, e, 6));
         const int64_t cand_items = std::min<int64_t>(n, (int64_t)na * (1 + S.avg_deg_ceil));
-        launch_merge(S.Gm, true, S.g, S.st, sink, other, grid_for(cand_items, 256 / S.Gm, S.maxgrid),
-                     ctx->stream);
-        if (S.profile) HIPCHK(ctx, hipEventRecord(ctx->pev[4], ctx->stream));
+        launch_merge(S.Gm, true, S.g, S.st, sink, other, S.hubd, grid_for(cand_items, 256 / S.Gm, S.maxgrid),
+                     ctx->stream,
+               kev(S, MF_K_MERGE_DENSE, e, 8));
+        if (S.hub_kernels) {
+            launch_merge_hubs(true, S.g, S.st, sink, other, S.hub_grid, ctx->stream,
+                   kev(S, MF_K_MERGE_HUB, e, 10));
+        }
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
         if (S.profile) {
-            const double c1 = elapsed(ctx->pev[0], ctx->pev[1]), md = elapsed(ctx->pev[1], ctx->pev[2]);
-            const double c2 = elapsed(ctx->pev[2], ctx->pev[3]), mm = elapsed(ctx->pev[3], ctx->pev[4]);
+            const Ctl &c = *ctx->ctl_host;
+            int64_t b[4];
+            round_bytes(S, c, b);
+            const double md = span(S, MF_K_DISCHARGE_DENSE, e, 2, 3), mm = span(S, MF_K_MERGE_DENSE, e, 8, 9);
             S.ms_dis += md;
             S.ms_mer += mm;
             S.n_dis++;
             S.n_mer++;
-            const Ctl &c = *ctx->ctl_host;
-            const int64_t p = c.pushes - S.last.pushes;
-            if (!list_ready) kernel_record(S, MF_K_COMPACT, c1, n + 4 * (int64_t)c.na);
-            kernel_record(S, MF_K_DISCHARGE_DENSE, md,
-                          40 * (c.dverts - S.last.dverts) + 13 * (c.dslots - S.last.dslots) + 16 * p);
-            kernel_record(S, MF_K_COMPACT, c2, n + 4 * (int64_t)c.nc);
-            kernel_record(S, MF_K_MERGE_DENSE, mm,
-                          41 * (c.mverts - S.last.mverts) + 4 * (c.mslots - S.last.mslots) + 12 * p);
+            if (!list_ready) kernel_record(S, MF_K_COMPACT, span(S, MF_K_COMPACT, e, 0, 1), n + 4 * (int64_t)c.na);
+            kernel_record(S, MF_K_DISCHARGE_DENSE, md, b[0]);
+            kernel_record(S, MF_K_COMPACT, span(S, MF_K_COMPACT, e, 6, 7), n + 4 * (int64_t)c.nc);
+            kernel_record(S, MF_K_MERGE_DENSE, mm, b[2]);
+            if (S.hub_kernels) {
+                kernel_record(S, MF_K_DISCHARGE_HUB, span(S, MF_K_DISCHARGE_HUB, e, 4, 5), b[1]);
+                kernel_record(S, MF_K_MERGE_HUB, span(S, MF_K_MERGE_HUB, e, 10, 11), b[3]);
+            }
             S.last = c;
         }
         S.dense_rounds++;
@@ -871,7 +957,14 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.dense_threshold = std::min<int64_t>(65536, std::max<int64_t>(2048, dg->n / 512));
     S.bu_factor = 8;
     S.hubdeg = 64 * S.Gb;
+    // Rounds discharge and merge vertices other than s and t only (a push
+    // into s needs a label of n + 1 in the first phase, and the sink of a
+    // phase takes its pushes directly).
+    S.hub_kernels = dg->maxdeg_inner > 64 * S.G;
+    S.hubd = S.hub_kernels ? 64 * S.G : 0x7fffffff;
+    S.hub_grid = ctx->num_cus * 2;
     S.profile = (o.flags & MF_PROFILE) != 0;
+    S.pmask = o.profile_mask ? o.profile_mask : 0xffffffffu;
     S.persistent = (o.flags & MF_PERSISTENT) != 0;
     if (o.dense_threshold > 0) S.dense_threshold = o.dense_threshold;
 
@@ -881,7 +974,8 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     launch_init_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
     launch_saturate(S.g, S.st, ctx->num_cus * 4, ctx->stream);
     launch_compact_flags(S.st.touched, n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream);
-    launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, grid_for(n, 256 / S.Gm, S.maxgrid), ctx->stream);
+    launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, S.hubd, grid_for(n, 256 / S.Gm, S.maxgrid), ctx->stream);
+    if (S.hub_kernels) launch_merge_hubs(true, S.g, S.st, dg->t, dg->s, S.hub_grid, ctx->stream);
 
     PhaseStats p1;
     int64_t cum[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // persistent-mode counters

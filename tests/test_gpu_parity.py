@@ -213,3 +213,26 @@ def test_persistent_grid_size(ctx, bpc):
     g = make_config("c4a", 16)
     _note(f"blocks_per_cu={bpc}")
     _compare(ctx, g, blocks_per_cu=bpc, check_a=False, persistent=True)
+
+
+def _star_graph(k, seed):
+    """s -> hub (cap big), hub -> leaf_i (random caps), leaf_i -> t (random
+    caps), plus leaf_i -> leaf_{i+1} arcs: one vertex of degree ~2k."""
+    rng = np.random.default_rng(seed)
+    n = k + 3
+    s, hub, t = 0, 1, n - 1
+    leaves = np.arange(2, 2 + k)
+    u = np.concatenate([[s], np.full(k, hub), leaves, leaves[:-1]])
+    v = np.concatenate([[hub], leaves, np.full(k, t), leaves[1:]])
+    c = np.concatenate([[10**6], rng.integers(1, 50, k), rng.integers(1, 50, k), rng.integers(0, 20, k - 1)])
+    return from_pairs(n, u, v, c, np.zeros(len(c), int), s, t, m_arcs=len(c))
+
+
+@pytest.mark.parametrize("name,f,lanes", [("c4b", 16, 32), ("c4b", 16, 1), ("c4b", 32, 4), ("star", 3000, 4),
+                                          ("star", 700, 1)])
+def test_hub_vertices_by_blocks(ctx, name, f, lanes):
+    """Vertices above 64 lanes' worth of slots are discharged and merged by a
+    block each; results stay those of the oracle."""
+    g = _star_graph(f, 7) if name == "star" else make_config(name, f)
+    _note(f"hub kernels {name}/{f} lanes={lanes}")
+    _compare(ctx, g, lanes=lanes, check_a=False)
