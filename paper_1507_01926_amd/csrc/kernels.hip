@@ -181,6 +181,10 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
         st.ctl->na2 = 0;
         st.ctl->bfs_empty_level = 0x7fffffff;
         st.ctl->gr_found = 0;
+        st.ctl->gr_found_deg = 0;
+        st.ctl->fdeg[0] = g.off[sink + 1] - g.off[sink];
+        st.ctl->fdeg[1] = 0;
+        st.ctl->fdeg[2] = 0;
     }
 }
 
@@ -191,11 +195,12 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
 template <int G>
 __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int level, int sink,
                                                int other, const int32_t *__restrict__ qin,
-                                               int32_t *__restrict__ qout, int hubdeg)
+                                               int32_t *__restrict__ qout, int hubdeg, int track_deg)
 {
     const int nq = st.ctl->nq[level % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.ctl->nq[(level + 2) % 3] = 0;
+        st.ctl->fdeg[(level + 2) % 3] = 0;
         st.ctl->nh[(level + 1) % 3] = 0;
         if (nq == 0) atomicMin(&st.ctl->bfs_empty_level, level);
     }
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
     const int next = level + 1;
-    int64_t gslots = 0;
+    int64_t gslots = 0, cdeg = 0;
     int claims = 0;
     MF_STAGE(stage);
     stage_init(stage);
@@ -225,6 +230,7 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
                     if (atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
                         claims++;
+                        if (track_deg) cdeg += g.off[w + 1] - g.off[w];
                         st.dn[w] = next;
                     }
                 }
@@ -235,15 +241,19 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
     stage_flush(stage, qout, &st.ctl->nq[next % 3]);
     block_add64(gslots, &st.ctl->gslots);
     block_add64(claims, &st.ctl->gr_found);
+    if (track_deg) {
+        block_add64(cdeg, &st.ctl->fdeg[next % 3]);
+        block_add64(cdeg, &st.ctl->gr_found_deg);
+    }
 }
 
 // The hub vertices of a top-down level, each expanded by every block.
 __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int level, int sink,
-                                                int other, int32_t *__restrict__ qout)
+                                                int other, int32_t *__restrict__ qout, int track_deg)
 {
     const int nh = st.ctl->nh[level % 3];
     const int next = level + 1;
-    int64_t gslots = 0;
+    int64_t gslots = 0, cdeg = 0;
     int claims = 0;
     MF_STAGE(stage);
     stage_init(stage);
@@ -261,6 +271,7 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
                     if (atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
                         claims++;
+                        if (track_deg) cdeg += g.off[w + 1] - g.off[w];
                         st.dn[w] = next;
                     }
                 }
@@ -271,17 +282,22 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
     stage_flush(stage, qout, &st.ctl->nq[next % 3]);
     block_add64(gslots, &st.ctl->hslots);
     block_add64(claims, &st.ctl->gr_found);
+    if (track_deg) {
+        block_add64(cdeg, &st.ctl->fdeg[next % 3]);
+        block_add64(cdeg, &st.ctl->gr_found_deg);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_gr_bu(GraphView g, StateView st, int level, int sink, int other)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.ctl->nq[(level + 2) % 3] = 0;
+        st.ctl->fdeg[(level + 2) % 3] = 0;
         st.ctl->nh[(level + 1) % 3] = 0;
     }
     const int next = level + 1;
     int found = 0;
-    int64_t gslots = 0;
+    int64_t gslots = 0, cdeg = 0;
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < g.n; w += gridDim.x * blockDim.x) {
         if (st.d[w] != g.n || w == sink || w == other) continue;
         const int beg = g.off[w], end = g.off[w + 1];
@@ -291,12 +307,15 @@ __global__ __launch_bounds__(256) void k_gr_bu(GraphView g, StateView st, int le
                 st.d[w] = next;
                 st.dn[w] = next;
                 found++;
+                cdeg += end - beg;
                 break;
             }
         }
     }
     block_add32(found, &st.ctl->nq[next % 3]);
     block_add64(gslots, &st.ctl->gslots);
+    block_add64(cdeg, &st.ctl->fdeg[next % 3]);
+    block_add64(cdeg, &st.ctl->gr_found_deg);
 }
 
 // Frontier list of a level from the labels (after a bottom-up level).
@@ -666,17 +685,17 @@ void launch_merge_hubs(bool dense, GraphView g, StateView st, int sink, int othe
 }
 
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
-                  int32_t *qout, int hubdeg, int grid, hipStream_t s, KEv ev)
+                  int32_t *qout, int hubdeg, int track_deg, int grid, hipStream_t s, KEv ev)
 {
-#define C_(X) MF_LAUNCH((k_gr_td<X>), grid, s, ev, g, st, level, sink, other, qin, qout, hubdeg)
+#define C_(X) MF_LAUNCH((k_gr_td<X>), grid, s, ev, g, st, level, sink, other, qin, qout, hubdeg, track_deg)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }
 
-void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int grid,
-                   hipStream_t s, KEv ev)
+void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int track_deg,
+                   int grid, hipStream_t s, KEv ev)
 {
-    MF_LAUNCH(k_gr_hub, grid, s, ev, g, st, level, sink, other, qout);
+    MF_LAUNCH(k_gr_hub, grid, s, ev, g, st, level, sink, other, qout, track_deg);
 }
 void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s, KEv ev)
 {

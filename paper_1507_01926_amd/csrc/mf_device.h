@@ -47,6 +47,10 @@ struct Ctl {
     // the counters of the hub kernels
     int32_t nhd, nhm;
     int64_t dh_verts, dh_slots, dh_pushes, mh_verts, mh_slots;
+    // global relabel: out-degree sum of each BFS frontier (ring by level % 3)
+    // and of every vertex labelled so far (edge-based direction choice)
+    int64_t fdeg[3];
+    int64_t gr_found_deg;
 };
 
 // Per-solve state.  Every array lives in device memory.

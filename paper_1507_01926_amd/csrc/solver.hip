@@ -38,9 +38,9 @@ void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta
 void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int hubd, int grid,
                   hipStream_t s, KEv ev = KEv());
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
-                  int32_t *qout, int hubdeg, int grid, hipStream_t s, KEv ev = KEv());
-void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int grid,
-                   hipStream_t s, KEv ev = KEv());
+                  int32_t *qout, int hubdeg, int track_deg, int grid, hipStream_t s, KEv ev = KEv());
+void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int track_deg,
+                   int grid, hipStream_t s, KEv ev = KEv());
 void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s,
                   KEv ev = KEv());
 void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s);
@@ -522,8 +522,14 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
     const int deg_sink = sink == S.dg->s ? S.dg->deg_s : S.dg->deg_t;
     const bool hub_first = deg_sink > S.hubdeg;
     const bool hub_later = S.dg->maxdeg_inner > S.hubdeg;
+    // Direction choice: a level runs bottom-up when its frontier holds more
+    // than 1/bu_factor of the unvisited vertices, or, in graphs with hub
+    // vertices, when the frontier's slots exceed 1/14 of the slots of the
+    // unvisited vertices (a few frontier vertices of very high degree).
+    int64_t fdeg = deg_sink;                       // slots of the current frontier
+    int64_t unexplored = S.g.slots - deg_sink;     // slots of the vertices not yet labelled
     while (nq > 0) {
-        const bool bottom_up = nq * S.bu_factor > unvisited;
+        const bool bottom_up = nq * S.bu_factor > unvisited || (hub_later && fdeg * 14 > unexplored);
         if (!bottom_up && have_list) {
             // A batch of top-down levels with one readback at its end; the
             // levels after the one that empties the frontier return at once.
@@ -539,11 +545,11 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             }
             for (int j = 0; j < K; j++) {
                 const int L = level + j;
-                launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, grid, ctx->stream,
+                launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, hub_later, grid, ctx->stream,
                        kev(S, MF_K_GR_TOPDOWN, ctx->lev.data(), 2 * nl));
                 kinds[nl++] = MF_K_GR_TOPDOWN;
                 if (L == 0 ? hub_first : hub_later) {
-                    launch_gr_hub(S.g, S.st, L, sink, other, qout, ctx->num_cus * 2, ctx->stream,
+                    launch_gr_hub(S.g, S.st, L, sink, other, qout, hub_later, ctx->num_cus * 2, ctx->stream,
                            kev(S, MF_K_GR_HUB, ctx->lev.data(), 2 * nl));
                     kinds[nl++] = MF_K_GR_HUB;
                 }
@@ -577,6 +583,8 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             S.td_levels += ran;
             unvisited -= found;
             found_before = c.gr_found;
+            unexplored = S.g.slots - deg_sink - c.gr_found_deg;
+            fdeg = ended ? 0 : c.fdeg[(level + K) % 3];
             level += ran;
             batch = nq_next > 2 * nq ? 1 : std::min(32, 2 * batch);
             nq = nq_next;
@@ -593,11 +601,11 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             S.td_levels++;
             HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
             launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
-            launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg,
+            launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg, hub_later,
                          grid_for(nq, groups, S.maxgrid), ctx->stream,
                    kev(S, MF_K_GR_TOPDOWN, ctx->pev, 4));
             if (hubs) {
-                launch_gr_hub(S.g, S.st, level, sink, other, qout, ctx->num_cus * 2, ctx->stream,
+                launch_gr_hub(S.g, S.st, level, sink, other, qout, hub_later, ctx->num_cus * 2, ctx->stream,
                        kev(S, MF_K_GR_HUB, ctx->pev, 6));
             }
             std::swap(qin, qout);
@@ -628,6 +636,8 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             S.last = c;
         }
         found_before = c.gr_found;
+        unexplored = S.g.slots - deg_sink - c.gr_found_deg;
+        fdeg = c.fdeg[(level + 1) % 3];
         nq = found;
         unvisited -= nq;
         level++;
