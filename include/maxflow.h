@@ -84,6 +84,14 @@ typedef struct {
                                   (the default); both give identical results.  On MI355X the
                                   launches are faster for one large instance: each grid barrier
                                   costs a cache write-back and invalidation per block */
+#define MF_GRID_PATH    0x8u   /* solve small graphs with the grid-wide kernels too; by default a
+                                  graph of at most MF_SMALL_N vertices and MF_SMALL_SLOTS slots is
+                                  solved by one workgroup in a single launch (the batched form's
+                                  kernel), which avoids a host round trip per round (measured
+                                  faster up to about 16K slots, slower above); both give
+                                  identical results */
+#define MF_SMALL_N      8192
+#define MF_SMALL_SLOTS  16384
 
 typedef struct {
     /* Global-relabel schedule (Sec. 3 and its footnote): a global relabel
@@ -158,7 +166,8 @@ typedef enum {
     MF_K_COMPACT = 7,
     MF_K_DISCHARGE_HUB = 8,
     MF_K_MERGE_HUB = 9,
-    MF_K_COUNT = 10
+    MF_K_BLOCK_SOLVE = 10,     /* a small graph's whole solve by one workgroup (no byte model) */
+    MF_K_COUNT = 11
 } mf_kernel_id;
 
 typedef struct mf_context mf_context;

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "MF_OK", 1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: 
 MF_PREFLOW_ONLY = 0x1
 MF_PROFILE = 0x2
 MF_PERSISTENT = 0x4
+MF_GRID_PATH = 0x8
 
 
 class MaxflowError(RuntimeError):
@@ -62,7 +63,7 @@ class mf_stats(ctypes.Structure):
 
 # kernel names of mf_stats.kernel_* in index order (mf_kernel_id)
 KERNEL_NAMES = ("k_discharge_list", "k_discharge_dense", "k_merge_list", "k_merge_dense", "k_gr_td",
-                "k_gr_hub", "k_gr_bu", "k_compact_flags", "k_discharge_hubs", "k_merge_hubs")
+                "k_gr_hub", "k_gr_bu", "k_compact_flags", "k_discharge_hubs", "k_merge_hubs", "k_batch")
 
 
 class mf_result(ctypes.Structure):
@@ -150,6 +151,8 @@ def options(**kw) -> mf_options:
             o.flags = (o.flags | MF_PROFILE) if v else (o.flags & ~MF_PROFILE)
         elif k == "persistent":
             o.flags = (o.flags | MF_PERSISTENT) if v else (o.flags & ~MF_PERSISTENT)
+        elif k == "grid_path":
+            o.flags = (o.flags | MF_GRID_PATH) if v else (o.flags & ~MF_GRID_PATH)
         else:
             setattr(o, k, int(v))
     return o

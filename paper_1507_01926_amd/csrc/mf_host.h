@@ -62,6 +62,7 @@ struct mf_context {
     hipEvent_t bev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> lev;     // profiling of batched levels, created on first use
     Workspace ws;
+    uint8_t *one = nullptr;    // device: item, result, queue and order of a single-workgroup solve
     int num_cus = 256;
     std::string err;
 };

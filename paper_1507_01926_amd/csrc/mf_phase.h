@@ -60,6 +60,7 @@ struct BatchResult {
     int64_t value, cut, rounds, rounds2, grs, grs2, levels, pushes, relabels;
     int64_t t_start, t_end;          // wall-clock ticks
     int64_t t_solve;                 // served: when the pull and checks ended
+    int64_t t_phase1;                // when the maximum preflow was reached
     int32_t status, block;
 };
 

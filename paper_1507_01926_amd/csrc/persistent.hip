@@ -573,6 +573,7 @@ __device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *ou
     int status = run_phase_team<G>(tm, stage, g, st, P, ctl + 1, ctl + 4);
     tm.sync();
     BatchResult r{};
+    if (threadIdx.x == 0) r.t_phase1 = wall_clock64();
     r.rounds = ctl[4].p_rounds;
     r.grs = ctl[4].p_grs;
     r.levels = ctl[4].p_levels;
@@ -605,6 +606,9 @@ __device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *ou
         r.grs2 = ctl[4].p_grs;
         if (it.flow)
             for (int a = threadIdx.x; a < g.slots; a += blockDim.x) it.flow[a] = g.cap[a] - st.res[a];
+    } else if (status == 1 && it.flow) {
+        // round limit: the flow output holds the preflow reached
+        for (int a = threadIdx.x; a < g.slots; a += blockDim.x) it.flow[a] = g.cap[a] - st.res[a];
     }
     r.status = status;
     tm.sync();

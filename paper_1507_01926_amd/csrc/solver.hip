@@ -174,6 +174,7 @@ void mf_context_destroy(mf_context *ctx)
         if (p) (void)hipFree(p);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
     if (ctx->bar) (void)hipFree(ctx->bar);
+    if (ctx->one) (void)hipFree(ctx->one);
     if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
     for (auto ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -916,6 +917,93 @@ static mf_status check_options(mf_context *ctx, const mf_options *o)
     return MF_OK;
 }
 
+// A small graph solved by one workgroup in a single launch: the batched
+// form's kernel on one instance, over the context's workspace.  Its rounds
+// are those of the grid-wide path (each round is a function of its start
+// state), without a host round trip per round or level.
+static mf_status solve_small(mf_context *ctx, mf_dgraph *dg, const mf_options &o, int64_t *value,
+                             int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats)
+{
+    const size_t oi = 0, orr = align256(sizeof(BatchItem)), oq = orr + align256(sizeof(BatchResult)),
+                 oo = oq + align256(sizeof(BatchQueue)), total = oo + 256;
+    if (!ctx->one) {
+        mf_status st = dalloc(ctx, (void **)&ctx->one, total);
+        if (st != MF_OK) return st;
+    }
+    Workspace &w = ctx->ws;
+    std::vector<uint8_t> host(total, 0);
+    BatchItem &it = *(BatchItem *)(host.data() + oi);
+    it.g = dg->view();
+    StateView &sv = it.st;
+    sv.res = w.res;
+    sv.delta = w.delta;
+    sv.d = w.d;
+    sv.dn = w.dn;
+    sv.owner = w.owner;
+    sv.e = w.e;
+    sv.act = w.act;
+    sv.touched = w.touched;
+    sv.H = w.H;
+    sv.A = w.A;
+    sv.A2 = w.A2;
+    sv.C = w.C;
+    sv.Q = w.Q;
+    sv.Q2 = w.Q2;
+    it.ctl = ctx->ctl;
+    it.flow = flow_dev;
+    it.side = side_dev ? side_dev : w.side;
+    it.G = batch_lanes(o.lanes_per_vertex, dg->n, dg->slots);
+    it.preflow_only = (o.flags & MF_PREFLOW_ONLY) ? 1 : 0;
+    PhaseParams &P = it.p;
+    P.freq_num = o.gr_freq_num;
+    P.freq_den = o.gr_freq_den;
+    P.alpha = o.gr_alpha;
+    P.beta = o.gr_beta;
+    P.round_charge = o.gr_round_charge;
+    P.max_rounds = o.max_rounds;
+    P.dense_threshold = o.dense_threshold > 0 ? o.dense_threshold : std::max<int64_t>(512, dg->n / 16);
+    P.bu_factor = 8;
+    P.hubdeg = 64 * it.G;
+    P.limit_ticks = 0;
+    BatchQueue &q = *(BatchQueue *)(host.data() + oq);
+    q.next = 0;
+    q.count = 1;
+    uint8_t *dev = ctx->one;
+    HIPCHK(ctx, hipMemcpyAsync(dev, host.data(), total, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    HIPCHK(ctx, launch_batch(it.G, 1, (const BatchItem *)(dev + oi), (const int32_t *)(dev + oo),
+                             (BatchResult *)(dev + orr), (BatchQueue *)(dev + oq), ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    BatchResult r;
+    HIPCHK(ctx, hipMemcpyAsync(&r, dev + orr, sizeof r, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (r.status != 0 && r.status != 1) return fail(ctx, MF_EDEVICE, "single-workgroup solve failed (%d)", r.status);
+    if (value) *value = r.value;
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->value = r.value;
+        stats->cut_capacity = r.cut;
+        stats->rounds = r.rounds;
+        stats->global_relabels = r.grs;
+        stats->bfs_levels = r.levels;
+        stats->rounds2 = r.rounds2;
+        stats->global_relabels2 = r.grs2;
+        stats->pushes = r.pushes;
+        stats->relabels = r.relabels;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]);
+        stats->ms_total = ms;
+        stats->ms_preflow = 1e3 * (double)(r.t_phase1 - r.t_start) / (double)ctx->wall_hz;
+        stats->ms_phase_kernel = ms;
+        stats->phase_launches = 1;
+        if (o.flags & MF_PROFILE) {
+            stats->kernel_ms[MF_K_BLOCK_SOLVE] = ms;
+            stats->kernel_launches[MF_K_BLOCK_SOLVE] = 1;
+        }
+    }
+    return r.status == 1 ? fail(ctx, MF_ETIMEOUT, "round limit %lld reached", (long long)o.max_rounds) : MF_OK;
+}
+
 extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt,
                                        int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
                                        mf_stats *stats)
@@ -932,6 +1020,8 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     if (preflow_only && flow_dev) return fail(ctx, MF_EINVAL, "flow output requires phase 2");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     if ((st = ensure_workspace(ctx, dg->n, dg->slots)) != MF_OK) return st;
+    if (!(o.flags & (MF_PERSISTENT | MF_GRID_PATH)) && dg->n <= MF_SMALL_N && dg->slots <= MF_SMALL_SLOTS)
+        return solve_small(ctx, dg, o, value, flow_dev, side_dev, stats);
 
     Solve S;
     memset(&S.last, 0, sizeof S.last);

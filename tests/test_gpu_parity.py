@@ -59,16 +59,20 @@ def _compare(ctx, g, sched=None, lanes=0, check_a=True, **extra):
     return r
 
 
-def test_hand_traced_example(ctx):
+@pytest.mark.parametrize("grid_path", [False, True])
+def test_hand_traced_example(ctx, grid_path):
+    """Small graphs run on one workgroup by default; grid_path forces the
+    grid-wide kernels.  Both must reproduce the hand trace."""
     import paper_1507_01926_amd as mf
     gold = json.load(open(os.path.join(GOLDEN, "prsn_two_vertex_trace.json")))
     g = graph_from_json(gold["graph"])
     cap = np.array(gold["graph"]["cap"])
     for lanes in (1, 2, 4, 64):
-        r1 = ctx.solve(g, mf.options(max_rounds=1, lanes_per_vertex=lanes), allow_timeout=True)
+        r1 = ctx.solve(g, mf.options(max_rounds=1, lanes_per_vertex=lanes, grid_path=grid_path),
+                       allow_timeout=True)
         assert r1["status"] == mf.MF_ETIMEOUT
         assert (cap - r1["flow"]).tolist() == gold["after_round_1"]["res"]
-        r = ctx.solve(g, mf.options(lanes_per_vertex=lanes))
+        r = ctx.solve(g, mf.options(lanes_per_vertex=lanes, grid_path=grid_path))
         ph = gold["phase1"]
         assert r["value"] == ph["value"] and r["rounds"] == ph["rounds"]
         assert r["pushes"] == ph["pushes"] and r["relabels"] == ph["relabels"]
@@ -78,21 +82,24 @@ def test_hand_traced_example(ctx):
         assert r["flow"].tolist() == gold["phase2"]["flow"]
 
 
+@pytest.mark.parametrize("grid_path", [False, True])
 @pytest.mark.parametrize("chunk", range(4))
-def test_random_small_graphs(ctx, chunk):
+def test_random_small_graphs(ctx, chunk, grid_path):
     for seed in range(chunk * 40, chunk * 40 + 40):
         n = 4 + seed % 30
         g = random_graph(n, (2 + seed % 5) * n, seed, cap_max=50)
-        _note(f"random seed={seed} n={n} slots={g.slots}")
-        _compare(ctx, g, lanes=[0, 1, 2, 8, 64][seed % 5])
+        _note(f"random seed={seed} n={n} slots={g.slots} grid_path={grid_path}")
+        _compare(ctx, g, lanes=[0, 1, 2, 8, 64][seed % 5], grid_path=grid_path)
 
 
 @pytest.mark.parametrize("name,f", [("c1", 1), ("c2", 16), ("c3", 8), ("c4a", 32), ("c4b", 16),
-                                    ("c2", 8), ("c4a", 16)])
+                                    ("c2", 8), ("c4a", 16), ("c2", 64), ("c3", 32), ("c4b", 128)])
 def test_families_scaled(ctx, name, f):
     g = make_config(name, f)
     _note(f"family {name}/{f} n={g.n} slots={g.slots}")
     _compare(ctx, g)
+    if g.n <= 8192:
+        _compare(ctx, g, grid_path=True, check_a=False)
 
 
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
