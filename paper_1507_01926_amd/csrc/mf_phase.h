@@ -64,6 +64,11 @@ struct BatchResult {
     int32_t status, block;
 };
 
+// Threads of a workgroup that solves one instance (batched and served forms,
+// small graphs): 512 threads fit one workgroup per compute unit at the
+// solver's register count and give each instance twice the lanes of 256.
+constexpr int BATCH_BLOCK = 512;
+
 struct BatchQueue {
     int32_t next;     // next position of `order` to hand out
     int32_t count;    // number of positions

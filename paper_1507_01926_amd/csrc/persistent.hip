@@ -624,7 +624,7 @@ __device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *ou
 // One launch per lane count G: items[order[0 .. count)] are the instances of
 // this launch.
 template <int G>
-__global__ __launch_bounds__(256) void k_batch(const BatchItem *items, const int32_t *order,
+__global__ __launch_bounds__(BATCH_BLOCK) void k_batch(const BatchItem *items, const int32_t *order,
                                                BatchResult *results, BatchQueue *q)
 {
     __shared__ int32_t sbuf[STAGE_CAP];
@@ -648,10 +648,10 @@ hipError_t launch_batch(int G, int grid, const BatchItem *items, const int32_t *
                         BatchQueue *q, hipStream_t s)
 {
     switch (G) {
-    case 4: hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
-    case 8: hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
-    case 16: hipLaunchKernelGGL(k_batch<16>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
-    default: hipLaunchKernelGGL(k_batch<32>, dim3(grid), dim3(256), 0, s, items, order, results, q); break;
+    case 4: hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(BATCH_BLOCK), 0, s, items, order, results, q); break;
+    case 8: hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(BATCH_BLOCK), 0, s, items, order, results, q); break;
+    case 16: hipLaunchKernelGGL(k_batch<16>, dim3(grid), dim3(BATCH_BLOCK), 0, s, items, order, results, q); break;
+    default: hipLaunchKernelGGL(k_batch<32>, dim3(grid), dim3(BATCH_BLOCK), 0, s, items, order, results, q); break;
     }
     return hipGetLastError();
 }
@@ -693,7 +693,7 @@ __device__ __forceinline__ void solve_block_any(const BatchItem &it, BatchResult
 // when the host asks for shutdown or when no request has arrived for
 // idle_ticks, so every wave exits.
 template <int G>
-__global__ __launch_bounds__(256) void k_serve(ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, int epoch)
+__global__ __launch_bounds__(BATCH_BLOCK) void k_serve(ServeHostQueue *hq, int32_t *next, uint64_t idle_ticks, int epoch)
 {
     __shared__ int32_t sbuf[STAGE_CAP];
     __shared__ int32_t scnt, sbase;
@@ -795,11 +795,11 @@ hipError_t launch_serve(int G, int grid, ServeHostQueue *hq, int32_t *next, uint
                         hipStream_t s)
 {
     switch (G) {
-    case 0: hipLaunchKernelGGL(k_serve<0>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
-    case 4: hipLaunchKernelGGL(k_serve<4>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
-    case 8: hipLaunchKernelGGL(k_serve<8>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
-    case 16: hipLaunchKernelGGL(k_serve<16>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
-    default: hipLaunchKernelGGL(k_serve<32>, dim3(grid), dim3(256), 0, s, hq, next, idle_ticks, epoch); break;
+    case 0: hipLaunchKernelGGL(k_serve<0>, dim3(grid), dim3(BATCH_BLOCK), 0, s, hq, next, idle_ticks, epoch); break;
+    case 4: hipLaunchKernelGGL(k_serve<4>, dim3(grid), dim3(BATCH_BLOCK), 0, s, hq, next, idle_ticks, epoch); break;
+    case 8: hipLaunchKernelGGL(k_serve<8>, dim3(grid), dim3(BATCH_BLOCK), 0, s, hq, next, idle_ticks, epoch); break;
+    case 16: hipLaunchKernelGGL(k_serve<16>, dim3(grid), dim3(BATCH_BLOCK), 0, s, hq, next, idle_ticks, epoch); break;
+    default: hipLaunchKernelGGL(k_serve<32>, dim3(grid), dim3(BATCH_BLOCK), 0, s, hq, next, idle_ticks, epoch); break;
     }
     return hipGetLastError();
 }
@@ -810,7 +810,7 @@ int serve_blocks_per_cu(int G)
     const void *f = G == 0 ? (const void *)k_serve<0> : G == 4 ? (const void *)k_serve<4>
                   : G == 8 ? (const void *)k_serve<8> : G == 16 ? (const void *)k_serve<16>
                   : (const void *)k_serve<32>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, BATCH_BLOCK, 0) != hipSuccess) return 0;
     return nb;
 }
 
@@ -819,7 +819,7 @@ int batch_blocks_per_cu(int G)
     int nb = 0;
     const void *f = G == 4 ? (const void *)k_batch<4> : G == 8 ? (const void *)k_batch<8>
                   : G == 16 ? (const void *)k_batch<16> : (const void *)k_batch<32>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, BATCH_BLOCK, 0) != hipSuccess) return 0;
     return nb;
 }
 
