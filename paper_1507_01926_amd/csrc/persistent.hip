@@ -624,8 +624,9 @@ __device__ __forceinline__ void solve_block(const BatchItem &it, BatchResult *ou
 // One launch per lane count G: items[order[0 .. count)] are the instances of
 // this launch.
 template <int G>
-__global__ __launch_bounds__(BATCH_BLOCK) void k_batch(const BatchItem *items, const int32_t *order,
-                                               BatchResult *results, BatchQueue *q)
+__global__ __launch_bounds__(BATCH_BLOCK) void k_batch(const BatchItem *__restrict__ items,
+                                                       const int32_t *__restrict__ order,
+                                                       BatchResult *results, BatchQueue *q)
 {
     __shared__ int32_t sbuf[STAGE_CAP];
     __shared__ int32_t scnt, sbase;
@@ -634,10 +635,12 @@ __global__ __launch_bounds__(BATCH_BLOCK) void k_batch(const BatchItem *items, c
     while (true) {
         if (threadIdx.x == 0) s_i = atomicAdd(&q->next, 1);
         __syncthreads();
-        const int j = s_i;
+        // instance indices are block-uniform: keep them (and the descriptor
+        // loads through them) in scalar registers
+        const int j = __builtin_amdgcn_readfirstlane(s_i);
         __syncthreads();
         if (j >= count) break;
-        const int i = order[j];
+        const int i = __builtin_amdgcn_readfirstlane(order[j]);
         if (threadIdx.x == 0) results[i].t_start = wall_clock64();
         solve_block<G>(items[i], &results[i], sbuf, &scnt, &sbase);
         __syncthreads();
@@ -769,9 +772,18 @@ __global__ __launch_bounds__(BATCH_BLOCK) void k_serve(ServeHostQueue *hq, int32
             }
         }
         __syncthreads();
-        const int i = s_i;
+        const int i = __builtin_amdgcn_readfirstlane(s_i);
         if (i < 0) break;
-        const BatchItem it = s_item;
+        // the descriptor is the same for the whole block: read it into scalar
+        // registers (its pointers then need no vector registers)
+        BatchItem it;
+        {
+            static_assert(sizeof(BatchItem) % 4 == 0, "descriptor of 32-bit words");
+            const int *src = (const int *)&s_item;
+            int *dst = (int *)&it;
+#pragma unroll
+            for (int k = 0; k < (int)(sizeof(BatchItem) / 4); k++) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+        }
         if (block_prepare(it)) {
             if (threadIdx.x == 0) s_res.t_solve = wall_clock64();
             solve_block_any<G>(it, &s_res, sbuf, &scnt, &sbase);
