@@ -35,12 +35,17 @@ WORKLOADS = {
 }
 
 
-def tuned_schedule(g) -> dict:
+def tuned_schedule(g, level_charge: int = 0) -> dict:
     """Global-relabel schedule used by the benchmark: the paper's rule (freq
     1/2, alpha 6, beta 12) plus a per-round work charge of (12n+2m)/128, which
-    bounds the rounds between two global relabels."""
+    bounds the rounds between two global relabels, and optionally a charge
+    per breadth-first level of the last relabel (for graphs whose searches
+    run thousands of levels deep)."""
     thr = 12 * g.n + 2 * g.slots
-    return dict(gr_round_charge=max(1, thr // 128))
+    sched = dict(gr_round_charge=max(1, thr // 128))
+    if level_charge:
+        sched["gr_level_charge"] = int(level_charge)
+    return sched
 
 
 def kernel_source_sha() -> str:
@@ -201,6 +206,8 @@ def main():
                     help="run each phase as one persistent cooperative kernel instead of one launch per round")
     ap.add_argument("--paper-schedule", action="store_true",
                     help="use the paper's global-relabel rule without the per-round charge")
+    ap.add_argument("--level-charge", type=int, default=0,
+                    help="global-relabel threshold charge per level of the last relabel's search")
     ap.add_argument("--stream", type=int, default=256,
                     help="instances of the batched/served stream leg (0 = skip)")
     ap.add_argument("--stream-nmax", type=float, default=1e5)
@@ -219,7 +226,7 @@ def main():
 
     print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
     g = make_config(args.workload)
-    sched = {} if args.paper_schedule else tuned_schedule(g)
+    sched = {} if args.paper_schedule else tuned_schedule(g, args.level_charge)
     ctx = mf.Context(0)
     dg = ctx.upload(g)                       # residency + validation: not timed
     dev = torch.device("cuda:0")
@@ -236,12 +243,13 @@ def main():
         out = {}
         for i, name in enumerate(mf.KERNEL_NAMES):
             out[name] = (sum(r["kernel_ms"][i] for r in rs), sum(r["kernel_bytes"][i] for r in rs),
-                         sum(r["kernel_launches"][i] for r in rs))
+                         sum(r["kernel_launches"][i] for r in rs), sum(r["kernel_timed"][i] for r in rs))
         return out
 
     # Warm-up solves time every kernel with HIP events and name the dominant
-    # one; the timed solves then bracket only that kernel's launches (an
-    # event costs device time, so timing all of them would slow the solves).
+    # one; the timed solves then bracket only that kernel's launches, and of
+    # a kernel launched thousands of times per solve only every 16th launch
+    # (an event pair costs a few microseconds of device time).
     print(f"[bench] warmup x{args.warmup}", file=sys.stderr, flush=True)
     warm = [dg.solve(opt, flow.data_ptr(), side.data_ptr()) for _ in range(args.warmup)]
     torch.cuda.synchronize()
@@ -250,6 +258,7 @@ def main():
         wk = per_kernel(warm[-1:])
         dom_idx = mf.KERNEL_NAMES.index(max(wk, key=lambda k: wk[k][0]))
         opt.profile_mask = 1 << dom_idx
+        opt.profile_stride = 16 if wk[mf.KERNEL_NAMES[dom_idx]][2] >= 256 else 1
     print(f"[bench] timing x{args.steps}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     runs = []
@@ -269,11 +278,12 @@ def main():
     if args.persistent:
         # one cooperative kernel per phase does all the work of the rounds
         kernels = {"k_phase": (tot["ms_phase_kernel"], tot["discharge_bytes"] + tot["merge_bytes"]
-                               + tot["global_relabel_bytes"], tot["phase_launches"])}
+                               + tot["global_relabel_bytes"], tot["phase_launches"], tot["phase_launches"])}
         table, table_steps = kernels, args.steps
     dom = mf.KERNEL_NAMES[dom_idx] if dom_idx is not None else max(kernels, key=lambda k: kernels[k][0])
-    ms_k, bytes_k, launches_k = kernels[dom]
-    achieved = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
+    ms_k, bytes_k, launches_k, timed_k = kernels[dom]
+    avg_launch_ms = ms_k / max(1, timed_k)
+    achieved = bytes_k / max(1, launches_k) / (avg_launch_ms * 1e-3) / 1e9 if ms_k > 0 else 0.0
     alg_bytes_total = tot["discharge_bytes"] + tot["merge_bytes"] + tot["global_relabel_bytes"]
     r0 = runs[0]
     line = {
@@ -297,7 +307,8 @@ def main():
                      "traffic": measured_traffic(dom, args.workload),
                      "launches_per_step": launches_k / args.steps,
                      "alg_bytes_per_launch": bytes_k / max(1, launches_k),
-                     "avg_launch_us": 1e3 * ms_k / max(1, launches_k)},
+                     "avg_launch_us": 1e3 * avg_launch_ms,
+                     "launches_timed": timed_k},
         "solve": {"value": r0["value"], "cut_capacity": r0["cut_capacity"],
                   "value_equals_cut": r0["value"] == r0["cut_capacity"],
                   "rounds": r0["rounds"], "rounds_phase2": r0["rounds2"],
@@ -306,7 +317,8 @@ def main():
                   "ms_preflow": sum(r["ms_preflow"] for r in runs) / len(runs),
                   "preflow_arcs_per_s": g.m_arcs / (1e-3 * sum(r["ms_preflow"] for r in runs) / len(runs)),
                   "kernels_per_step": {k: {"ms": v[0] / table_steps, "launches": v[2] / table_steps,
-                                           "alg_GBps": (v[1] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
+                                           "alg_GBps": (v[1] / v[2] / (v[0] / v[3] * 1e-3) / 1e9)
+                                           if v[0] > 0 and v[3] > 0 else None}
                                        for k, v in table.items() if v[2] > 0},
                   "kernels_per_step_note": "event-timed in the last warm-up solve (every kernel timed)"
                                            if table is not kernels else "event-timed in the timed solves",

@@ -98,8 +98,12 @@ typedef struct {
      * runs when gr_freq_num * W > gr_freq_den * (gr_alpha * n + slots), where
      * W is the relabel work since the last one (each relabel of v adds
      * outdeg(v) + gr_beta) plus gr_round_charge per round.  The paper's
-     * constants are freq = 1/2, alpha = 6, beta = 12 and no round charge. */
-    int64_t gr_freq_num, gr_freq_den, gr_alpha, gr_beta, gr_round_charge;
+     * constants are freq = 1/2, alpha = 6, beta = 12 and no round charge.
+     * gr_level_charge adds gr_level_charge * L to the right-hand side, L
+     * being the depth of the phase's last global relabel: on a GPU a
+     * relabel costs about a launch per breadth-first level, so deep
+     * searches are run less often (0 = the paper's rule). */
+    int64_t gr_freq_num, gr_freq_den, gr_alpha, gr_beta, gr_round_charge, gr_level_charge;
     int64_t max_rounds;          /* 0 = unlimited; counts rounds of phase 1 */
     uint32_t flags;
     int32_t lanes_per_vertex;    /* lanes that discharge one vertex: 0 = automatic, else 1..64, power of 2 */
@@ -112,6 +116,12 @@ typedef struct {
                                     timed with HIP events; 0 = all.  Events cost device time, so a
                                     caller timing a solve restricts them to the kernel it studies;
                                     bytes and launch counts are kept for every kernel */
+    int32_t bfs_bottom_up_factor; /* a breadth-first level of the global relabel runs bottom-up
+                                    (every unlabelled vertex looks for a labelled neighbour) when
+                                    frontier * factor > unlabelled vertices: 0 = automatic (8) */
+    int32_t profile_stride;      /* with MF_PROFILE: time every profile_stride-th launch of each
+                                    timed kernel (0 or 1 = every launch), which bounds the device
+                                    time the events cost; counts and bytes cover every launch */
     int32_t reserved[1];
 } mf_options;
 
@@ -134,11 +144,14 @@ typedef struct {
     double ms_phase_kernel;
     int64_t phase_launches;
     /* with MF_PROFILE, per kernel (index: mf_kernel_id): summed durations of
-     * its launches (HIP events recorded around each launch on the context's
-     * stream), number of launches and algorithmic bytes of those launches */
+     * its timed launches (HIP events recorded from each launch's dispatch on
+     * the context's stream), number of launches and algorithmic bytes of all
+     * its launches, and the number of launches timed */
     double kernel_ms[12];
     int64_t kernel_launches[12];
     int64_t kernel_bytes[12];
+    int64_t kernel_timed[12];    /* launches whose durations make up kernel_ms (all of them, or
+                                    every profile_stride-th one) */
 } mf_stats;
 
 /* Kernels of the host-driven path that mf_stats profiles one by one.

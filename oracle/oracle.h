@@ -90,6 +90,9 @@ typedef struct {
      * into them); 0: rebuild the working set at every global relabel and
      * stop only after one that finds no active vertex */
     int64_t literal_termination;
+    /* added to alpha * n + m per level of the last global relabel's
+     * breadth-first search (0 in the paper's rule) */
+    int64_t level_charge;
 } og_sched;
 
 int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,

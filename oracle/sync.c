@@ -44,8 +44,9 @@ typedef struct {
     int64_t pushes, relabels, grs, rounds, work_total, levels;
 } sync_state;
 
-/* Listing 2: level-synchronous BFS from the sink over the reverse residual graph. */
-static void GlobalRelabel(sync_state *S, int64_t sink, int64_t other)
+/* Listing 2: level-synchronous BFS from the sink over the reverse residual
+ * graph.  Returns its depth (the largest label it gives). */
+static int64_t GlobalRelabel(sync_state *S, int64_t sink, int64_t other)
 {
     const og_graph *g = S->g;
     int64_t n = S->n;
@@ -75,6 +76,7 @@ static void GlobalRelabel(sync_state *S, int64_t sink, int64_t other)
     S->levels += level;
     S->grs++;
     for (int64_t v = 0; v < n; v++) S->dprime[v] = S->d[v];
+    return level;
 }
 
 static void touch_vertex(sync_state *S, int64_t v)
@@ -94,14 +96,17 @@ static int prsn_phase(sync_state *S, int64_t sink, int64_t other, int64_t max_ro
     const int64_t beta = sc->beta;
     int grPending = 1;                     /* workSinceLastGR := infinity */
     int64_t workSinceLastGR = 0;
+    int64_t lastDepth = 0;                 /* depth of the last global relabel */
     int64_t rounds_here = 0;
     while (1) {
         int justRelabeled = 0;
-        /* freq * workSinceLastGR > alpha * n + m */
-        if (grPending || sc->freq_num * workSinceLastGR > sc->freq_den * (sc->alpha * n + S->m)) {
+        /* freq * workSinceLastGR > alpha * n + m (+ level_charge * depth of
+         * the last global relabel, 0 in the paper's rule) */
+        if (grPending || sc->freq_num * workSinceLastGR >
+                             sc->freq_den * (sc->alpha * n + S->m + sc->level_charge * lastDepth)) {
             grPending = 0;
             workSinceLastGR = 0;
-            GlobalRelabel(S, sink, other);
+            lastDepth = GlobalRelabel(S, sink, other);
             if (sc->literal_termination) {
                 int64_t k = 0;
                 for (int64_t i = 0; i < S->nws; i++)
@@ -224,9 +229,10 @@ int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,
 {
     int rc = og_validate(g);
     if (rc) return rc;
-    og_sched sc = {1, 2, 6, 12, 0, 0};
+    og_sched sc = {1, 2, 6, 12, 0, 0, 0};
     if (sched) sc = *sched;
-    if (sc.freq_den <= 0 || sc.freq_num < 0 || sc.alpha < 0 || sc.beta < 0 || sc.round_charge < 0)
+    if (sc.freq_den <= 0 || sc.freq_num < 0 || sc.alpha < 0 || sc.beta < 0 || sc.round_charge < 0 ||
+        sc.level_charge < 0)
         return OG_ESIZE;
     int64_t n = g->n, M = g->slots > 0 ? g->slots : 1;
     sync_state S;

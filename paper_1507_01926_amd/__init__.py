@@ -41,11 +41,13 @@ class mf_graph(ctypes.Structure):
 class mf_options(ctypes.Structure):
     _fields_ = [("gr_freq_num", ctypes.c_int64), ("gr_freq_den", ctypes.c_int64),
                 ("gr_alpha", ctypes.c_int64), ("gr_beta", ctypes.c_int64),
-                ("gr_round_charge", ctypes.c_int64), ("max_rounds", ctypes.c_int64),
+                ("gr_round_charge", ctypes.c_int64), ("gr_level_charge", ctypes.c_int64),
+                ("max_rounds", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("lanes_per_vertex", ctypes.c_int32),
                 ("lanes_per_merge", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_bfs", ctypes.c_int32),
-                ("profile_mask", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 1)]
+                ("profile_mask", ctypes.c_uint32), ("bfs_bottom_up_factor", ctypes.c_int32),
+                ("profile_stride", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class mf_stats(ctypes.Structure):
@@ -59,7 +61,7 @@ class mf_stats(ctypes.Structure):
         "merge_bytes", "global_relabel_bytes")] + [
         ("ms_phase_kernel", ctypes.c_double), ("phase_launches", ctypes.c_int64),
         ("kernel_ms", ctypes.c_double * 12), ("kernel_launches", ctypes.c_int64 * 12),
-        ("kernel_bytes", ctypes.c_int64 * 12)]
+        ("kernel_bytes", ctypes.c_int64 * 12), ("kernel_timed", ctypes.c_int64 * 12)]
 
 # kernel names of mf_stats.kernel_* in index order (mf_kernel_id)
 KERNEL_NAMES = ("k_discharge_list", "k_discharge_dense", "k_merge_list", "k_merge_dense", "k_gr_td",

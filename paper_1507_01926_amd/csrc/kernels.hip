@@ -191,59 +191,89 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
 // Top-down level.  Levels may be launched several at a time without the host
 // reading the frontier sizes in between: a level whose frontier is empty
 // records itself in bfs_empty_level and returns (every later level is empty
-// too, since it finds nothing to expand).
+// too, since it finds nothing to expand).  Each non-empty level adds its
+// frontier size to gr_found, from which the host derives the vertices a batch
+// of levels labelled.
+//
+// Flags: TD_TRACK_DEG sums the slots of the claimed vertices (the
+// direction choice on graphs with hubs), TD_COUNT_SLOTS the slots expanded
+// (profiling), TD_EAGER reads the reverse residual of every slot together
+// with the neighbour's label instead of after it, which takes one dependent
+// load off the level's critical path at the cost of the reads for labelled
+// neighbours (used for small frontiers, where latency bounds the level).
+constexpr int TD_TRACK_DEG = 1, TD_COUNT_SLOTS = 2, TD_EAGER = 4;
+
 template <int G>
 __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int level, int sink,
                                                int other, const int32_t *__restrict__ qin,
-                                               int32_t *__restrict__ qout, int hubdeg, int track_deg)
+                                               int32_t *__restrict__ qout, int hubdeg, int flags)
 {
     const int nq = st.ctl->nq[level % 3];
+    const int gl = threadIdx.x & (G - 1);
+    const int groups = blockDim.x / G;
+    const int stride = gridDim.x * groups;
+    const int next = level + 1;
+    int i = blockIdx.x * groups + threadIdx.x / G;
+    // The first entry is read together with the frontier size (the queue
+    // holds n entries, so the read stays in bounds; entries past the
+    // frontier are not used).
+    int v = i < g.n ? qin[i] : 0;
+    __shared__ unsigned long long s_slots, s_cdeg;
+    if (threadIdx.x == 0) {
+        s_slots = 0;
+        s_cdeg = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.ctl->nq[(level + 2) % 3] = 0;
         st.ctl->fdeg[(level + 2) % 3] = 0;
         st.ctl->nh[(level + 1) % 3] = 0;
         if (nq == 0) atomicMin(&st.ctl->bfs_empty_level, level);
+        else atomicAdd((unsigned long long *)&st.ctl->gr_found, (unsigned long long)nq);
     }
     if (nq == 0) return;
-    const int gl = threadIdx.x & (G - 1);
-    const int groups = blockDim.x / G;
-    const int next = level + 1;
-    int64_t gslots = 0, cdeg = 0;
-    int claims = 0;
     MF_STAGE(stage);
     stage_init(stage);
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < nq; i += gridDim.x * groups) {
-        const int v = qin[i];
+    while (i < nq) {
+        const int inext = i + stride;
+        const int vnext = inext < nq ? qin[inext] : 0;
         const int beg = g.off[v], end = g.off[v + 1];
         if (end - beg > hubdeg) {
             wave_append(gl == 0, v, st.H, &st.ctl->nh[level % 3]);
-            continue;
-        }
-        if (gl == 0) gslots += end - beg;
-        for (int base = beg; base < end; base += G) {
-            const int a = base + gl;
-            bool claim = false;
-            int w = 0;
-            if (a < end) {
-                w = g.head[a];
-                if (w != sink && w != other && st.d[w] == g.n && st.res[g.rev[a]] > 0) {
-                    if (atomicCAS(&st.d[w], g.n, next) == g.n) {
+        } else {
+            if ((flags & TD_COUNT_SLOTS) && gl == 0) atomicAdd(&s_slots, (unsigned long long)(end - beg));
+            for (int base = beg; base < end; base += G) {
+                const int a = base + gl;
+                bool claim = false;
+                int w = 0;
+                if (a < end) {
+                    w = g.head[a];
+                    bool open;
+                    if (flags & TD_EAGER) {
+                        const int r = st.res[g.rev[a]];
+                        open = st.d[w] == g.n && r > 0;
+                    } else {
+                        open = st.d[w] == g.n && st.res[g.rev[a]] > 0;
+                    }
+                    if (open && w != sink && w != other && atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
-                        claims++;
-                        if (track_deg) cdeg += g.off[w + 1] - g.off[w];
+                        if (flags & TD_TRACK_DEG)
+                            atomicAdd(&s_cdeg, (unsigned long long)(g.off[w + 1] - g.off[w]));
                         st.dn[w] = next;
                     }
                 }
+                stage_append(stage, claim, w, qout, &st.ctl->nq[next % 3]);
             }
-            stage_append(stage, claim, w, qout, &st.ctl->nq[next % 3]);
         }
+        i = inext;
+        v = vnext;
     }
     stage_flush(stage, qout, &st.ctl->nq[next % 3]);
-    block_add64(gslots, &st.ctl->gslots);
-    block_add64(claims, &st.ctl->gr_found);
-    if (track_deg) {
-        block_add64(cdeg, &st.ctl->fdeg[next % 3]);
-        block_add64(cdeg, &st.ctl->gr_found_deg);
+    if (threadIdx.x == 0) {
+        if (flags & TD_COUNT_SLOTS) atomicAdd((unsigned long long *)&st.ctl->gslots, s_slots);
+        if ((flags & TD_TRACK_DEG) && s_cdeg) {
+            atomicAdd((unsigned long long *)&st.ctl->fdeg[next % 3], s_cdeg);
+            atomicAdd((unsigned long long *)&st.ctl->gr_found_deg, s_cdeg);
+        }
     }
 }
 
@@ -254,7 +284,6 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
     const int nh = st.ctl->nh[level % 3];
     const int next = level + 1;
     int64_t gslots = 0, cdeg = 0;
-    int claims = 0;
     MF_STAGE(stage);
     stage_init(stage);
     for (int h = 0; h < nh; h++) {
@@ -270,7 +299,6 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
                 if (w != sink && w != other && st.d[w] == g.n && st.res[g.rev[a]] > 0) {
                     if (atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
-                        claims++;
                         if (track_deg) cdeg += g.off[w + 1] - g.off[w];
                         st.dn[w] = next;
                     }
@@ -281,7 +309,6 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
     }
     stage_flush(stage, qout, &st.ctl->nq[next % 3]);
     block_add64(gslots, &st.ctl->hslots);
-    block_add64(claims, &st.ctl->gr_found);
     if (track_deg) {
         block_add64(cdeg, &st.ctl->fdeg[next % 3]);
         block_add64(cdeg, &st.ctl->gr_found_deg);
@@ -685,9 +712,9 @@ void launch_merge_hubs(bool dense, GraphView g, StateView st, int sink, int othe
 }
 
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
-                  int32_t *qout, int hubdeg, int track_deg, int grid, hipStream_t s, KEv ev)
+                  int32_t *qout, int hubdeg, int flags, int grid, hipStream_t s, KEv ev)
 {
-#define C_(X) MF_LAUNCH((k_gr_td<X>), grid, s, ev, g, st, level, sink, other, qin, qout, hubdeg, track_deg)
+#define C_(X) MF_LAUNCH((k_gr_td<X>), grid, s, ev, g, st, level, sink, other, qin, qout, hubdeg, flags)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }

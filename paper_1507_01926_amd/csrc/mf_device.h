@@ -38,7 +38,7 @@ struct Ctl {
     int32_t maxdeg_inner;  // largest out-degree over vertices other than s and t
     int32_t deg_s, deg_t;  // out-degrees of s and t
     int32_t bfs_empty_level;   // first top-down level of this relabel that found its frontier empty
-    int64_t gr_found;      // vertices labelled by top-down levels and hub expansions of this relabel
+    int64_t gr_found;      // sum of the frontier sizes of the top-down levels of this relabel
     // speculative list rounds: rounds run since the batch began, the stop
     // flag (set by the round that ends the batch) and the relabel work W
     int32_t batch_rounds, batch_stop;

@@ -27,7 +27,7 @@ struct GridBar {
 
 struct PhaseParams {
     int sink, other;
-    int64_t freq_num, freq_den, alpha, beta, round_charge, max_rounds;
+    int64_t freq_num, freq_den, alpha, beta, round_charge, level_charge, max_rounds;
     int64_t dense_threshold, bu_factor;
     int hubdeg;
     uint64_t limit_ticks;    // grid-barrier wait limit in wall-clock ticks

@@ -112,6 +112,7 @@ __device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const 
     const RoundParams rp{P.beta, sink};
 
     int64_t W = 0;
+    int64_t depth = 0;           // depth of the last global relabel
     bool force = true;
     int count = 0;
     bool dense = false;
@@ -121,7 +122,7 @@ __device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const 
 
     while (true) {
         bool just = false;
-        if (force || P.freq_num * W > P.freq_den * (P.alpha * n + m)) {
+        if (force || P.freq_num * W > P.freq_den * (P.alpha * n + m + P.level_charge * depth)) {
             // ---------------- global relabel ----------------
             for (int v = gtid; v < n; v += gthreads) {
                 const int lab = v == sink ? 0 : n;
@@ -240,6 +241,7 @@ __device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const 
                 level = next;
             }
             levels += level - 1;
+            depth = level - 1;
             grs++;
             // working set: every non-terminal vertex with excess and label < n
             {

@@ -288,7 +288,7 @@ extern "C" mf_status mf_server_submit(mf_server *sv, const mf_graph *g, const mf
                           (int64_t)g->n + g->slots < 2147483647LL && g->s >= 0 && g->s < g->n && g->t >= 0 &&
                           g->t < g->n && g->s != g->t && g->offsets && (g->slots == 0 || (g->head && g->rev && g->cap)) &&
                           o.gr_freq_den > 0 && o.gr_freq_num >= 0 && o.gr_alpha >= 0 && o.gr_beta >= 0 &&
-                          o.gr_round_charge >= 0 && o.max_rounds >= 0;
+                          o.gr_round_charge >= 0 && o.gr_level_charge >= 0 && o.max_rounds >= 0;
     if (shape_ok) {
         r->G = batch_lanes(o.lanes_per_vertex, g->n, g->slots);
         r->queue = 0;        // one queue; the serve kernel handles every lane count
@@ -531,9 +531,10 @@ static bool admit(mf_server *sv, Request *r)
     it.p.alpha = o.gr_alpha;
     it.p.beta = o.gr_beta;
     it.p.round_charge = o.gr_round_charge;
+    it.p.level_charge = o.gr_level_charge;
     it.p.max_rounds = o.max_rounds;
     it.p.dense_threshold = o.dense_threshold > 0 ? o.dense_threshold : std::max<int64_t>(512, r->n / 16);
-    it.p.bu_factor = 8;
+    it.p.bu_factor = o.bfs_bottom_up_factor > 0 ? o.bfs_bottom_up_factor : 8;
     it.p.hubdeg = 64 * r->G;
     it.ctl = (Ctl *)(base + L.end);
     r->index = index;

@@ -38,7 +38,7 @@ void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta
 void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int hubd, int grid,
                   hipStream_t s, KEv ev = KEv());
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
-                  int32_t *qout, int hubdeg, int track_deg, int grid, hipStream_t s, KEv ev = KEv());
+                  int32_t *qout, int hubdeg, int flags, int grid, hipStream_t s, KEv ev = KEv());
 void launch_gr_hub(GraphView g, StateView st, int level, int sink, int other, int32_t *qout, int track_deg,
                    int grid, hipStream_t s, KEv ev = KEv());
 void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int grid, hipStream_t s,
@@ -85,12 +85,15 @@ void mf_options_default(mf_options *o)
     o->gr_alpha = 6;
     o->gr_beta = 12;
     o->gr_round_charge = 0;
+    o->gr_level_charge = 0;
     o->max_rounds = 0;
     o->flags = 0;
     o->lanes_per_vertex = 0;
     o->lanes_per_merge = 0;
     o->lanes_per_bfs = 0;
     o->profile_mask = 0;
+    o->bfs_bottom_up_factor = 0;
+    o->profile_stride = 0;
 }
 
 const char *mf_version(void) { return "mi355x-maxflow 0.1 (gfx950)"; }
@@ -418,6 +421,7 @@ struct Solve {
     int64_t avg_deg_ceil;
     int64_t dense_threshold;   // working sets larger than this run in dense mode
     int64_t bu_factor;         // bottom-up BFS level when frontier * bu_factor > unvisited
+    int64_t gr_depth = 0;      // depth of the last global relabel
     int hubdeg;                // frontier vertices above this degree are expanded by the grid
     bool profile;
     uint32_t pmask;            // kernels (bits of mf_kernel_id) timed with events under MF_PROFILE
@@ -428,15 +432,24 @@ struct Solve {
     int64_t dense_rounds = 0, bu_levels = 0, td_levels = 0, grs = 0;
     double kms[MF_K_COUNT] = {};         // per kernel: event time, launches, algorithmic bytes
     int64_t kn[MF_K_COUNT] = {}, kb[MF_K_COUNT] = {};
+    int64_t kt[MF_K_COUNT] = {};         // launches in kms
+    int64_t kissue[MF_K_COUNT] = {};     // launches issued, for the sampling stride
+    int64_t stride = 1;                  // time every stride-th launch of a timed kernel
+    std::vector<hipEvent_t> rec;         // start events of sampled launches not yet read
     Ctl last;                            // counters at the previous readback
 };
 
+// ms < 0: the launch was not sampled for timing (only its count and bytes).
 static void kernel_record(Solve &S, int k, double ms, int64_t bytes)
 {
-    S.kms[k] += ms;
+    if (ms >= 0) {
+        S.kms[k] += ms;
+        S.kt[k]++;
+    }
     S.kn[k]++;
     S.kb[k] += bytes;
 }
+static double timed_ms(double ms) { return ms > 0 ? ms : 0.0; }
 
 // Algorithmic bytes of the rounds since the last readback: discharge, hub
 // discharge, merge, hub merge (the per-unit model of mf_kernel_id).
@@ -464,18 +477,26 @@ static float elapsed(hipEvent_t a, hipEvent_t b)
 static bool timed(const Solve &S, int kind) { return S.profile && ((S.pmask >> kind) & 1u); }
 // ev: an event array (read only when the kernel is timed); the launch records
 // ev[i] and ev[i+1] from its own dispatch.
-static KEv kev(const Solve &S, int kind, const hipEvent_t *ev, int i)
+// Every stride-th launch of a timed kernel is sampled.
+static KEv kev(Solve &S, int kind, const hipEvent_t *ev, int i)
 {
     KEv k;
-    if (timed(S, kind)) {
+    if (timed(S, kind) && S.kissue[kind]++ % S.stride == 0) {
         k.a = ev[i];
         k.b = ev[i + 1];
+        S.rec.push_back(ev[i]);
     }
     return k;
 }
-static double span(const Solve &S, int kind, const hipEvent_t *ev, int a, int b)
+// Duration of the launch that recorded ev[a] and ev[b], or -1 if it was not
+// sampled.
+static double span(Solve &S, int kind, const hipEvent_t *ev, int a, int b)
 {
-    return timed(S, kind) ? (double)elapsed(ev[a], ev[b]) : 0.0;
+    if (!timed(S, kind)) return -1.0;
+    auto it = std::find(S.rec.begin(), S.rec.end(), ev[a]);
+    if (it == S.rec.end()) return -1.0;
+    S.rec.erase(it);
+    return (double)elapsed(ev[a], ev[b]);
 }
 
 // Working-set representation for the next round: a list for small sets, the
@@ -499,6 +520,15 @@ static mf_status batch_events(mf_context *ctx, size_t count)
         ctx->lev.push_back(e);
     }
     return MF_OK;
+}
+
+// Flags of a top-down level (the TD_* flags of the kernel): degree tracking
+// on graphs with hubs, slot counts when profiling, and eager reverse-residual
+// reads for frontiers small enough that the level is latency-bound.
+static int td_flags(const Solve &S, bool track_deg, int64_t nq)
+{
+    constexpr int64_t EAGER_MAX = 16384;
+    return (track_deg ? 1 : 0) | (S.profile ? 2 : 0) | (nq <= EAGER_MAX ? 4 : 0);
 }
 
 static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, int &na, bool &dense)
@@ -544,9 +574,10 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
                 mf_status est = batch_events(ctx, 4 * 32);
                 if (est != MF_OK) return est;
             }
+            const int tdf = td_flags(S, hub_later, nq);
             for (int j = 0; j < K; j++) {
                 const int L = level + j;
-                launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, hub_later, grid, ctx->stream,
+                launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, tdf, grid, ctx->stream,
                        kev(S, MF_K_GR_TOPDOWN, ctx->lev.data(), 2 * nl));
                 kinds[nl++] = MF_K_GR_TOPDOWN;
                 if (L == 0 ? hub_first : hub_later) {
@@ -561,12 +592,13 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             const Ctl &c = *ctx->ctl_host;
             const bool ended = c.bfs_empty_level < level + K;
             const int ran = ended ? c.bfs_empty_level - level : K;   // levels with a non-empty frontier
-            const int64_t found = c.gr_found - found_before;
+            // each level adds its frontier size to gr_found, so the batch
+            // labelled the sum of its frontiers less the first plus the next
+            const int64_t frontier = c.gr_found - found_before;
             const int64_t nq_next = ended ? 0 : c.nq[(level + K) % 3];
+            const int64_t found = frontier - nq + nq_next;
             if (S.profile) {
-                // bytes by the model of each kernel; the frontier sizes of the
-                // batch add up to nq + found - nq_next
-                const int64_t frontier = nq + found - nq_next;
+                // bytes by the model of each kernel
                 int64_t td_bytes = 12 * frontier + 12 * (c.gslots - S.last.gslots) + 8 * found;
                 int64_t hub_bytes = 12 * (c.hslots - S.last.hslots);
                 for (int i = 0; i < nl; i++) {
@@ -576,7 +608,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
                     else { b = hub_bytes; hub_bytes = 0; }
                     const double ms = span(S, k, ctx->lev.data(), 2 * i, 2 * i + 1);
                     kernel_record(S, k, ms, b);
-                    S.ms_gr += ms;
+                    S.ms_gr += timed_ms(ms);
                 }
                 S.n_gr += ran;
                 S.last = c;
@@ -602,7 +634,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             S.td_levels++;
             HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
             launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
-            launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg, hub_later,
+            launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg, td_flags(S, hub_later, nq),
                          grid_for(nq, groups, S.maxgrid), ctx->stream,
                    kev(S, MF_K_GR_TOPDOWN, ctx->pev, 4));
             if (hubs) {
@@ -621,16 +653,16 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             const int64_t gs = c.gslots - S.last.gslots;
             if (bottom_up) {
                 const double ms = span(S, MF_K_GR_BOTTOMUP, ctx->pev, 4, 5);
-                S.ms_gr += ms;
+                S.ms_gr += timed_ms(ms);
                 kernel_record(S, MF_K_GR_BOTTOMUP, ms, 4 * (int64_t)n + 8 * unvisited + 12 * gs + 8 * found);
             } else {
                 const double ms_td = span(S, MF_K_GR_TOPDOWN, ctx->pev, 4, 5);
-                S.ms_gr += ms_td;
+                S.ms_gr += timed_ms(ms_td);
                 kernel_record(S, MF_K_GR_TOPDOWN, ms_td, 12 * nq + 12 * gs + 8 * found);
                 if (hubs) {
                     const int64_t nh = c.nh[level % 3];
                     const double ms_h = span(S, MF_K_GR_HUB, ctx->pev, 6, 7);
-                    S.ms_gr += ms_h;
+                    S.ms_gr += timed_ms(ms_h);
                     kernel_record(S, MF_K_GR_HUB, ms_h, 12 * nh + 12 * (c.hslots - S.last.hslots));
                 }
             }
@@ -644,6 +676,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
         level++;
     }
     ps.levels += level - 1;
+    S.gr_depth = level - 1;
     ps.grs++;
     S.grs++;
     launch_gr_rebuild(S.g, S.st, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream);
@@ -669,7 +702,8 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
     bool list_ready = false;     // the working set is listed in A (else only flagged in act)
     while (true) {
         bool just = false;
-        if (force || o.gr_freq_num * W > o.gr_freq_den * (o.gr_alpha * n + m)) {
+        const int64_t gr_thr = o.gr_alpha * n + m + o.gr_level_charge * S.gr_depth;
+        if (force || o.gr_freq_num * W > o.gr_freq_den * gr_thr) {
             mf_status st = global_relabel(S, sink, other, ps, na, dense);
             if (st != MF_OK) return st;
             list_ready = !dense;     // a list-mode working set was compacted from the flags
@@ -719,7 +753,8 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                            kev(S, MF_K_MERGE_HUB, e, q + 6));
                 }
                 launch_round_close(ctx->ctl, j == 0, W, o.gr_round_charge, o.gr_freq_num, o.gr_freq_den,
-                                   o.gr_alpha * n + m, S.dense_threshold, ctx->stream);
+                                   o.gr_alpha * n + m + o.gr_level_charge * S.gr_depth, S.dense_threshold,
+                                   ctx->stream);
                 std::swap(sj.A, sj.A2);
             }
             mf_status st = read_ctl(ctx);
@@ -740,15 +775,15 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                     const double mm = span(S, MF_K_MERGE_LIST, e, q + 4, q + 5);
                     kernel_record(S, MF_K_DISCHARGE_LIST, md, j == 0 ? b[0] : 0);
                     kernel_record(S, MF_K_MERGE_LIST, mm, j == 0 ? b[2] : 0);
-                    S.ms_dis += md;
-                    S.ms_mer += mm;
+                    S.ms_dis += timed_ms(md);
+                    S.ms_mer += timed_ms(mm);
                     if (S.hub_kernels) {
                         const double hd = span(S, MF_K_DISCHARGE_HUB, e, q + 2, q + 3);
                         const double hm = span(S, MF_K_MERGE_HUB, e, q + 6, q + 7);
                         kernel_record(S, MF_K_DISCHARGE_HUB, hd, j == 0 ? b[1] : 0);
                         kernel_record(S, MF_K_MERGE_HUB, hm, j == 0 ? b[3] : 0);
-                        S.ms_dis += hd;
-                        S.ms_mer += hm;
+                        S.ms_dis += timed_ms(hd);
+                        S.ms_mer += timed_ms(hm);
                     }
                 }
                 S.n_dis += K;
@@ -813,8 +848,8 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             int64_t b[4];
             round_bytes(S, c, b);
             const double md = span(S, MF_K_DISCHARGE_DENSE, e, 2, 3), mm = span(S, MF_K_MERGE_DENSE, e, 8, 9);
-            S.ms_dis += md;
-            S.ms_mer += mm;
+            S.ms_dis += timed_ms(md);
+            S.ms_mer += timed_ms(mm);
             S.n_dis++;
             S.n_mer++;
             if (!list_ready) kernel_record(S, MF_K_COMPACT, span(S, MF_K_COMPACT, e, 0, 1), n + 4 * (int64_t)c.na);
@@ -855,6 +890,7 @@ static mf_status run_phase_persistent(Solve &S, int sink, int other, int64_t max
     P.alpha = o.gr_alpha;
     P.beta = o.gr_beta;
     P.round_charge = o.gr_round_charge;
+    P.level_charge = o.gr_level_charge;
     P.max_rounds = max_rounds;
     P.dense_threshold = S.dense_threshold;
     P.bu_factor = S.bu_factor;
@@ -909,11 +945,15 @@ static mf_status ensure_batch_streams(mf_context *ctx)
 static mf_status check_options(mf_context *ctx, const mf_options *o)
 {
     if (o->gr_freq_den <= 0 || o->gr_freq_num < 0 || o->gr_alpha < 0 || o->gr_beta < 0 ||
-        o->gr_round_charge < 0 || o->max_rounds < 0)
+        o->gr_round_charge < 0 || o->gr_level_charge < 0 || o->max_rounds < 0)
         return fail(ctx, MF_EINVAL, "invalid global-relabel schedule");
     if (o->lanes_per_vertex < 0 || o->lanes_per_vertex > 64 || o->lanes_per_merge < 0 ||
         o->lanes_per_merge > 64 || o->lanes_per_bfs < 0 || o->lanes_per_bfs > 64)
         return fail(ctx, MF_EINVAL, "lane counts must be 0..64");
+    if (o->profile_stride < 0)
+        return fail(ctx, MF_EINVAL, "profile_stride must be >= 0");
+    if (o->bfs_bottom_up_factor < 0)
+        return fail(ctx, MF_EINVAL, "bfs_bottom_up_factor must be >= 0");
     return MF_OK;
 }
 
@@ -960,9 +1000,10 @@ static mf_status solve_small(mf_context *ctx, mf_dgraph *dg, const mf_options &o
     P.alpha = o.gr_alpha;
     P.beta = o.gr_beta;
     P.round_charge = o.gr_round_charge;
+    P.level_charge = o.gr_level_charge;
     P.max_rounds = o.max_rounds;
     P.dense_threshold = o.dense_threshold > 0 ? o.dense_threshold : std::max<int64_t>(512, dg->n / 16);
-    P.bu_factor = 8;
+    P.bu_factor = o.bfs_bottom_up_factor > 0 ? o.bfs_bottom_up_factor : 8;
     P.hubdeg = 64 * it.G;
     P.limit_ticks = 0;
     BatchQueue &q = *(BatchQueue *)(host.data() + oq);
@@ -998,6 +1039,7 @@ static mf_status solve_small(mf_context *ctx, mf_dgraph *dg, const mf_options &o
         stats->phase_launches = 1;
         if (o.flags & MF_PROFILE) {
             stats->kernel_ms[MF_K_BLOCK_SOLVE] = ms;
+            stats->kernel_timed[MF_K_BLOCK_SOLVE] = 1;
             stats->kernel_launches[MF_K_BLOCK_SOLVE] = 1;
         }
     }
@@ -1055,7 +1097,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.maxgrid = ctx->num_cus * 16;
     S.avg_deg_ceil = (dg->slots + dg->n - 1) / std::max<int64_t>(1, dg->n);
     S.dense_threshold = std::min<int64_t>(65536, std::max<int64_t>(2048, dg->n / 512));
-    S.bu_factor = 8;
+    S.bu_factor = o.bfs_bottom_up_factor > 0 ? o.bfs_bottom_up_factor : 8;
     S.hubdeg = 64 * S.Gb;
     // Rounds discharge and merge vertices other than s and t only (a push
     // into s needs a label of n + 1 in the first phase, and the sink of a
@@ -1065,6 +1107,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.hub_grid = ctx->num_cus * 2;
     S.profile = (o.flags & MF_PROFILE) != 0;
     S.pmask = o.profile_mask ? o.profile_mask : 0xffffffffu;
+    S.stride = o.profile_stride > 1 ? o.profile_stride : 1;
     S.persistent = (o.flags & MF_PERSISTENT) != 0;
     if (o.dense_threshold > 0) S.dense_threshold = o.dense_threshold;
 
@@ -1161,6 +1204,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
             stats->global_relabel_bytes = 12 * (c.gslots + c.hslots) + S.grs * 9 * (int64_t)n + S.bu_levels * 4 * (int64_t)n;
             for (int k = 0; k < MF_K_COUNT; k++) {
                 stats->kernel_ms[k] = S.kms[k];
+                stats->kernel_timed[k] = S.kt[k];
                 stats->kernel_launches[k] = S.kn[k];
                 stats->kernel_bytes[k] = S.kb[k];
             }
@@ -1343,9 +1387,10 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
         P.alpha = oi.gr_alpha;
         P.beta = oi.gr_beta;
         P.round_charge = oi.gr_round_charge;
+        P.level_charge = oi.gr_level_charge;
         P.max_rounds = oi.max_rounds;
         P.dense_threshold = oi.dense_threshold > 0 ? oi.dense_threshold : std::max<int64_t>(512, gh.n / 16);
-        P.bu_factor = 8;
+        P.bu_factor = oi.bfs_bottom_up_factor > 0 ? oi.bfs_bottom_up_factor : 8;
         P.hubdeg = 64 * it.G;
         P.limit_ticks = 0;
         it.preflow_only = (oi.flags & MF_PREFLOW_ONLY) ? 1 : 0;

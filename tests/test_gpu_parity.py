@@ -110,7 +110,8 @@ def test_lane_count_does_not_change_results(ctx, lanes):
 
 
 @pytest.mark.parametrize("sched", [dict(round_charge=5000), dict(freq_num=1, freq_den=1),
-                                   dict(alpha=1, beta=0), dict(round_charge=100000, alpha=30)])
+                                   dict(alpha=1, beta=0), dict(round_charge=100000, alpha=30),
+                                   dict(level_charge=20000), dict(level_charge=200000, round_charge=5000)])
 def test_schedules(ctx, sched):
     g = make_config("c3", 8)
     _note(f"schedule {sched}")
@@ -204,7 +205,7 @@ def test_persistent_mode_matches(ctx, name, f):
     g = make_config(name, f)
     _note(f"persistent {name}/{f}")
     _compare(ctx, g, persistent=True, check_a=False)
-    _compare(ctx, g, persistent=True, check_a=False, sched=dict(round_charge=20000))
+    _compare(ctx, g, persistent=True, check_a=False, sched=dict(round_charge=20000, level_charge=50000))
 
 
 @pytest.mark.parametrize("dense_threshold", [1, 64, 1 << 30])

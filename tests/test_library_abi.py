@@ -46,6 +46,7 @@ def test_defaults_are_the_papers_schedule():
     import paper_1507_01926_amd as mf
     o = mf.options()
     assert (o.gr_freq_num, o.gr_freq_den, o.gr_alpha, o.gr_beta, o.gr_round_charge) == (1, 2, 6, 12, 0)
+    assert o.gr_level_charge == 0 and o.bfs_bottom_up_factor == 0 and o.profile_stride == 0
 
 
 def test_no_device_fails_loudly():

@@ -229,11 +229,15 @@ def test_schedules_change_rounds_not_results():
     g = make_config("c2", 16)
     base = oracle.sync_maxflow(g)
     thr = 12 * g.n + 2 * g.slots
-    for sched in (dict(round_charge=thr // 100), dict(freq_num=1, freq_den=1), dict(alpha=30)):
+    grs = {base["global_relabels"]}
+    for sched in (dict(round_charge=thr // 100), dict(freq_num=1, freq_den=1), dict(alpha=30),
+                  dict(level_charge=thr // 8), dict(level_charge=thr, round_charge=thr // 100)):
         r = oracle.sync_maxflow(g, schedule=sched)
         assert r["value"] == base["value"]
         assert (r["tstar"] == base["tstar"]).all()
         _cert_ok(g, r["flow"], r["tstar"])
+        grs.add(r["global_relabels"])
+    assert len(grs) > 2          # the schedules do change how often the labels are recomputed
 
 
 def test_certificate_rejects_non_maximum_and_invalid():
