@@ -196,12 +196,14 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
 // of levels labelled.
 //
 // Flags: TD_TRACK_DEG sums the slots of the claimed vertices (the
-// direction choice on graphs with hubs), TD_COUNT_SLOTS the slots expanded
-// (profiling), TD_EAGER reads the reverse residual of every slot together
-// with the neighbour's label instead of after it, which takes one dependent
-// load off the level's critical path at the cost of the reads for labelled
-// neighbours (used for small frontiers, where latency bounds the level).
-constexpr int TD_TRACK_DEG = 1, TD_COUNT_SLOTS = 2, TD_EAGER = 4;
+// direction choice on graphs with hubs), TD_EAGER reads the reverse residual
+// of every slot together with the neighbour's label instead of after it,
+// which takes one dependent load off the level's critical path at the cost
+// of the reads for labelled neighbours (used for small frontiers, where
+// latency bounds the level).  The slots a level expands are not counted here
+// (a per-block count cost more than half the level's time); profiling gets
+// them from k_gr_slots once the relabel is done.
+constexpr int TD_TRACK_DEG = 1, TD_EAGER = 4;
 
 template <int G>
 __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int level, int sink,
@@ -218,11 +220,8 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
     // holds n entries, so the read stays in bounds; entries past the
     // frontier are not used).
     int v = i < g.n ? qin[i] : 0;
-    __shared__ unsigned long long s_slots, s_cdeg;
-    if (threadIdx.x == 0) {
-        s_slots = 0;
-        s_cdeg = 0;
-    }
+    __shared__ unsigned long long s_cdeg;
+    if (threadIdx.x == 0) s_cdeg = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.ctl->nq[(level + 2) % 3] = 0;
         st.ctl->fdeg[(level + 2) % 3] = 0;
@@ -240,7 +239,6 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
         if (end - beg > hubdeg) {
             wave_append(gl == 0, v, st.H, &st.ctl->nh[level % 3]);
         } else {
-            if ((flags & TD_COUNT_SLOTS) && gl == 0) atomicAdd(&s_slots, (unsigned long long)(end - beg));
             for (int base = beg; base < end; base += G) {
                 const int a = base + gl;
                 bool claim = false;
@@ -268,13 +266,31 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
         v = vnext;
     }
     stage_flush(stage, qout, &st.ctl->nq[next % 3]);
-    if (threadIdx.x == 0) {
-        if (flags & TD_COUNT_SLOTS) atomicAdd((unsigned long long *)&st.ctl->gslots, s_slots);
-        if ((flags & TD_TRACK_DEG) && s_cdeg) {
-            atomicAdd((unsigned long long *)&st.ctl->fdeg[next % 3], s_cdeg);
-            atomicAdd((unsigned long long *)&st.ctl->gr_found_deg, s_cdeg);
-        }
+    if (threadIdx.x == 0 && (flags & TD_TRACK_DEG) && s_cdeg) {
+        atomicAdd((unsigned long long *)&st.ctl->fdeg[next % 3], s_cdeg);
+        atomicAdd((unsigned long long *)&st.ctl->gr_found_deg, s_cdeg);
     }
+}
+
+// Profiling: slots of the vertices a finished relabel expanded top-down,
+// i.e. labelled vertices of degree at most hubdeg (hubs go to k_gr_hub),
+// without those whose level ran bottom-up.  With lv.count == 0 the kernel
+// adds the slots of every such labelled vertex to *out; otherwise it
+// subtracts those of the vertices whose label is one of lv.
+__global__ __launch_bounds__(256) void k_gr_slots(GraphView g, const int32_t *__restrict__ d, int hubdeg,
+                                                  LevelSet lv, int64_t *out)
+{
+    int64_t s = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const int L = d[v];
+        if (L >= g.n) continue;
+        const int deg = g.off[v + 1] - g.off[v];
+        if (deg > hubdeg) continue;
+        bool take = lv.count == 0;
+        for (int k = 0; k < lv.count; k++) take |= L == lv.lv[k];
+        if (take) s += deg;
+    }
+    block_add64(lv.count == 0 ? s : -s, out);
 }
 
 // The hub vertices of a top-down level, each expanded by every block.
@@ -765,6 +781,11 @@ void launch_saturate(GraphView g, StateView st, int grid, hipStream_t s)
 void launch_gr_init(GraphView g, StateView st, int sink, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gr_init, dim3(grid), dim3(256), 0, s, g, st, sink);
+}
+void launch_gr_slots(GraphView g, const int32_t *d, int hubdeg, LevelSet lv, int64_t *out, int grid,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gr_slots, dim3(grid), dim3(256), 0, s, g, d, hubdeg, lv, out);
 }
 void launch_gr_rebuild(GraphView g, StateView st, int sink, int other, int grid, hipStream_t s)
 {

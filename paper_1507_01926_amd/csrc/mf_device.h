@@ -51,6 +51,7 @@ struct Ctl {
     // and of every vertex labelled so far (edge-based direction choice)
     int64_t fdeg[3];
     int64_t gr_found_deg;
+    int64_t td_slots;      // profiling: slots expanded by the top-down levels of a relabel
 };
 
 // Per-solve state.  Every array lives in device memory.

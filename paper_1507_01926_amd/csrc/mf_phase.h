@@ -25,6 +25,12 @@ struct GridBar {
     int pad1[30];
 };
 
+// A short list of breadth-first levels (passed by value to k_gr_slots).
+struct LevelSet {
+    int count;
+    int lv[15];
+};
+
 struct PhaseParams {
     int sink, other;
     int64_t freq_num, freq_den, alpha, beta, round_charge, level_charge, max_rounds;

@@ -56,6 +56,8 @@ void launch_validate(GraphView g, Ctl *ctl, int grid, hipStream_t s);
 void launch_init_state(GraphView g, StateView st, int grid, hipStream_t s);
 void launch_saturate(GraphView g, StateView st, int grid, hipStream_t s);
 void launch_gr_init(GraphView g, StateView st, int sink, int grid, hipStream_t s);
+void launch_gr_slots(GraphView g, const int32_t *d, int hubdeg, LevelSet lv, int64_t *out, int grid,
+                     hipStream_t s);
 void launch_gr_rebuild(GraphView g, StateView st, int sink, int other, int grid, hipStream_t s);
 void launch_round_reset(Ctl *ctl, bool dense, hipStream_t s);
 void launch_round_end(Ctl *ctl, hipStream_t s);
@@ -422,6 +424,7 @@ struct Solve {
     int64_t dense_threshold;   // working sets larger than this run in dense mode
     int64_t bu_factor;         // bottom-up BFS level when frontier * bu_factor > unvisited
     int64_t gr_depth = 0;      // depth of the last global relabel
+    int64_t td_slots = 0;      // profiling: slots expanded by top-down levels
     int hubdeg;                // frontier vertices above this degree are expanded by the grid
     bool profile;
     uint32_t pmask;            // kernels (bits of mf_kernel_id) timed with events under MF_PROFILE
@@ -523,12 +526,12 @@ static mf_status batch_events(mf_context *ctx, size_t count)
 }
 
 // Flags of a top-down level (the TD_* flags of the kernel): degree tracking
-// on graphs with hubs, slot counts when profiling, and eager reverse-residual
-// reads for frontiers small enough that the level is latency-bound.
-static int td_flags(const Solve &S, bool track_deg, int64_t nq)
+// on graphs with hubs, and eager reverse-residual reads for frontiers small
+// enough that the level is latency-bound.
+static int td_flags(bool track_deg, int64_t nq)
 {
     constexpr int64_t EAGER_MAX = 16384;
-    return (track_deg ? 1 : 0) | (S.profile ? 2 : 0) | (nq <= EAGER_MAX ? 4 : 0);
+    return (track_deg ? 1 : 0) | (nq <= EAGER_MAX ? 4 : 0);
 }
 
 static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, int &na, bool &dense)
@@ -538,6 +541,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
     launch_gr_init(S.g, S.st, sink, grid_for(n, 256, S.maxgrid), ctx->stream);
     int64_t nq = 1;
     int64_t unvisited = n - 2;
+    std::vector<int> bu_lv;            // profiling: levels run bottom-up
     int64_t found_before = 0;          // gr_found at the last readback
     int level = 0;
     // Top-down levels launched per readback: 1 while the frontier grows
@@ -574,7 +578,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
                 mf_status est = batch_events(ctx, 4 * 32);
                 if (est != MF_OK) return est;
             }
-            const int tdf = td_flags(S, hub_later, nq);
+            const int tdf = td_flags(hub_later, nq);
             for (int j = 0; j < K; j++) {
                 const int L = level + j;
                 launch_gr_td(S.Gb, S.g, S.st, L, sink, other, qin, qout, S.hubdeg, tdf, grid, ctx->stream,
@@ -598,8 +602,9 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             const int64_t nq_next = ended ? 0 : c.nq[(level + K) % 3];
             const int64_t found = frontier - nq + nq_next;
             if (S.profile) {
-                // bytes by the model of each kernel
-                int64_t td_bytes = 12 * frontier + 12 * (c.gslots - S.last.gslots) + 8 * found;
+                // bytes by the model of each kernel (the slots the levels
+                // expanded are added once the relabel is done)
+                int64_t td_bytes = 12 * frontier + 8 * found;
                 int64_t hub_bytes = 12 * (c.hslots - S.last.hslots);
                 for (int i = 0; i < nl; i++) {
                     const int k = kinds[i];
@@ -627,6 +632,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
         const bool hubs = level == 0 ? hub_first : hub_later;
         if (bottom_up) {
             S.bu_levels++;
+            if (S.profile) bu_lv.push_back(level);
             launch_gr_bu(S.g, S.st, level, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream,
                    kev(S, MF_K_GR_BOTTOMUP, ctx->pev, 4));
             have_list = false;
@@ -634,7 +640,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             S.td_levels++;
             HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->nq[(level + 2) % 3], 0, sizeof(int32_t), ctx->stream));
             launch_gr_collect(S.g, S.st, level, qin, grid_for(n, 256, S.maxgrid), ctx->stream);
-            launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg, td_flags(S, hub_later, nq),
+            launch_gr_td(S.Gb, S.g, S.st, level, sink, other, qin, qout, S.hubdeg, td_flags(hub_later, nq),
                          grid_for(nq, groups, S.maxgrid), ctx->stream,
                    kev(S, MF_K_GR_TOPDOWN, ctx->pev, 4));
             if (hubs) {
@@ -658,7 +664,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             } else {
                 const double ms_td = span(S, MF_K_GR_TOPDOWN, ctx->pev, 4, 5);
                 S.ms_gr += timed_ms(ms_td);
-                kernel_record(S, MF_K_GR_TOPDOWN, ms_td, 12 * nq + 12 * gs + 8 * found);
+                kernel_record(S, MF_K_GR_TOPDOWN, ms_td, 12 * nq + 8 * found);
                 if (hubs) {
                     const int64_t nh = c.nh[level % 3];
                     const double ms_h = span(S, MF_K_GR_HUB, ctx->pev, 6, 7);
@@ -679,9 +685,27 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
     S.gr_depth = level - 1;
     ps.grs++;
     S.grs++;
+    if (S.profile) {
+        // slots expanded by the top-down levels: those of the labelled
+        // vertices, less those whose level ran bottom-up
+        const int grid = grid_for(n, 256, S.maxgrid);
+        HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->td_slots, 0, sizeof(int64_t), ctx->stream));
+        LevelSet all{};
+        launch_gr_slots(S.g, S.st.d, S.hubdeg, all, &ctx->ctl->td_slots, grid, ctx->stream);
+        for (size_t i = 0; i < bu_lv.size(); i += 15) {
+            LevelSet part{};
+            for (size_t k = i; k < bu_lv.size() && k < i + 15; k++) part.lv[part.count++] = bu_lv[k];
+            launch_gr_slots(S.g, S.st.d, S.hubdeg, part, &ctx->ctl->td_slots, grid, ctx->stream);
+        }
+    }
     launch_gr_rebuild(S.g, S.st, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream);
     mf_status st = read_ctl(ctx);
     if (st != MF_OK) return st;
+    if (S.profile) {
+        S.kb[MF_K_GR_TOPDOWN] += 12 * ctx->ctl_host->td_slots;
+        S.td_slots += ctx->ctl_host->td_slots;
+        S.last = *ctx->ctl_host;
+    }
     na = ctx->ctl_host->na2;
     prepare_working_set(S, na, false, dense);
     return MF_OK;
@@ -1201,7 +1225,8 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
             stats->global_relabel_launches = S.n_gr;
             stats->discharge_bytes = 40 * c.dverts + 13 * c.dslots + 16 * c.pushes + S.dense_rounds * (int64_t)n;
             stats->merge_bytes = 41 * c.mverts + 4 * c.mslots + 12 * c.pushes + S.dense_rounds * (int64_t)n;
-            stats->global_relabel_bytes = 12 * (c.gslots + c.hslots) + S.grs * 9 * (int64_t)n + S.bu_levels * 4 * (int64_t)n;
+            stats->global_relabel_bytes = 12 * (c.gslots + c.hslots + S.td_slots) + S.grs * 9 * (int64_t)n +
+                                          S.bu_levels * 4 * (int64_t)n;
             for (int k = 0; k < MF_K_COUNT; k++) {
                 stats->kernel_ms[k] = S.kms[k];
                 stats->kernel_timed[k] = S.kt[k];
