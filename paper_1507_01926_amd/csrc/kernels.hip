@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
         if (nq == 0) atomicMin(&st.ctl->bfs_empty_level, level);
         else atomicAdd((unsigned long long *)&st.ctl->gr_found, (unsigned long long)nq);
     }
-    if (nq == 0) return;
+    if (i - threadIdx.x / G >= nq) return;          // no frontier vertex for this block
     MF_STAGE(stage);
     stage_init(stage);
     while (i < nq) {
@@ -406,6 +406,7 @@ __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView s
     const int na = st.ctl->na;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
+    if (blockIdx.x * groups >= na) return;          // no vertex for this block
     DisAcc acc;
     for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups) {
         const int v = st.A[i];
@@ -429,6 +430,7 @@ __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView 
     const int na = st.ctl->na;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
+    if (blockIdx.x * groups >= na) return;          // no vertex for this block
     DisAcc acc;
     for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups) {
         const int v = st.A[i];
@@ -455,6 +457,7 @@ __global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, i
     const int nc = st.ctl->nc;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
+    if (blockIdx.x * groups >= nc) return;          // no vertex for this block
     MerAcc acc;
     MF_STAGE(stage);
     stage_init(stage);
@@ -478,6 +481,7 @@ __global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, 
     const int nc = st.ctl->nc;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
+    if (blockIdx.x * groups >= nc) return;          // no vertex for this block
     MerAcc acc;
     MF_STAGE(stage);
     stage_init(stage);
