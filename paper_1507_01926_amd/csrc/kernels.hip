@@ -16,7 +16,7 @@
 //                atomics), applies them to res and e, applies the new label
 //                and decides whether w is active in the next round.
 // A global relabel (Sec. 2.1, Sec. 3) is a level-synchronous reverse BFS from
-// the sink (k_gr_init, k_gr_level per level, k_gr_rebuild).
+// the sink (k_gr_init, then k_gr_td or k_gr_bu per level, k_gr_rebuild).
 #include <hip/hip_ext.h>
 
 #include "mf_device.h"
@@ -165,9 +165,7 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
 {
     const int stride = gridDim.x * blockDim.x;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
-        const int lab = v == sink ? 0 : g.n;
-        st.d[v] = lab;
-        st.dn[v] = lab;
+        st.d[v] = v == sink ? 0 : g.n;        // dn follows in k_gr_rebuild
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.Q[0] = sink;
@@ -256,7 +254,6 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
                         claim = true;
                         if (flags & TD_TRACK_DEG)
                             atomicAdd(&s_cdeg, (unsigned long long)(g.off[w + 1] - g.off[w]));
-                        st.dn[w] = next;
                     }
                 }
                 stage_append(stage, claim, w, qout, &st.ctl->nq[next % 3]);
@@ -316,7 +313,6 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
                     if (atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
                         if (track_deg) cdeg += g.off[w + 1] - g.off[w];
-                        st.dn[w] = next;
                     }
                 }
             }
@@ -348,7 +344,6 @@ __global__ __launch_bounds__(256) void k_gr_bu(GraphView g, StateView st, int le
             gslots++;
             if (st.res[a] > 0 && st.d[g.head[a]] == level) {
                 st.d[w] = next;
-                st.dn[w] = next;
                 found++;
                 cdeg += end - beg;
                 break;
@@ -377,11 +372,17 @@ __global__ __launch_bounds__(256) void k_gr_collect(GraphView g, StateView st, i
 
 // Working set after a global relabel: every vertex other than the two
 // terminals with positive excess and a label below n (dense flags + count).
+// After a global relabel: the round labels dn take the new labels (the
+// levels write only d, so the label copies are one coalesced pass here
+// instead of a scattered store per claimed vertex), and the working set is
+// every vertex other than the terminals with excess and a label below n.
 __global__ void k_gr_rebuild(GraphView g, StateView st, int sink, int other)
 {
     int cnt = 0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
-        const bool p = v != sink && v != other && st.e[v] > 0 && st.d[v] < g.n;
+        const int dv = st.d[v];
+        st.dn[v] = dv;
+        const bool p = v != sink && v != other && st.e[v] > 0 && dv < g.n;
         st.act[v] = p;
         cnt += p;
     }
