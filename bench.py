@@ -206,6 +206,8 @@ def main():
                     help="run each phase as one persistent cooperative kernel instead of one launch per round")
     ap.add_argument("--paper-schedule", action="store_true",
                     help="use the paper's global-relabel rule without the per-round charge")
+    ap.add_argument("--simple-rounds", action="store_true",
+                    help="rounds of the simple synchronous variant of Sec. 3 (ablation of Listing 1's rounds)")
     ap.add_argument("--level-charge", type=int, default=0,
                     help="global-relabel threshold charge per level of the last relabel's search")
     ap.add_argument("--stream", type=int, default=256,
@@ -232,7 +234,7 @@ def main():
     dev = torch.device("cuda:0")
     flow = torch.empty(max(1, g.slots), dtype=torch.int32, device=dev)
     side = torch.empty(g.n, dtype=torch.uint8, device=dev)
-    opt = mf.options(profile=True, persistent=args.persistent, **sched)
+    opt = mf.options(profile=True, persistent=args.persistent, simple_rounds=args.simple_rounds, **sched)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -301,7 +303,9 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "n": g.n, "arcs": g.m_arcs, "slots": g.slots,
-                   "schedule": sched or "paper (freq 1/2, alpha 6, beta 12)"},
+                   "schedule": sched or "paper (freq 1/2, alpha 6, beta 12)",
+                   "rounds": "simple synchronous variant (Sec. 3)" if args.simple_rounds
+                             else "Listing 1 (win criterion, full discharge)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, args.workload),

@@ -90,6 +90,13 @@ typedef struct {
                                   kernel), which avoids a host round trip per round (measured
                                   faster up to about 16K slots, slower above); both give
                                   identical results */
+#define MF_SIMPLE_ROUNDS 0x10u  /* rounds of the simple synchronous variant that Sec. 3 starts from
+                                  (the paper's first design): every active vertex makes one pass
+                                  over its arcs, pushing on every admissible arc with no win
+                                  criterion, and then at most one relabel; excess changes and new
+                                  labels apply at the round's end as in the default rounds.  Value,
+                                  cut and sink side are the same; rounds, pushes and per-slot flow
+                                  differ */
 #define MF_SMALL_N      8192
 #define MF_SMALL_SLOTS  16384
 

@@ -33,11 +33,11 @@ class _OgGraph(ctypes.Structure):
 class _OgSched(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "freq_num", "freq_den", "alpha", "beta", "round_charge", "literal_termination",
-        "level_charge")]
+        "level_charge", "simple")]
 
 
 PAPER_SCHEDULE = dict(freq_num=1, freq_den=2, alpha=6, beta=12, round_charge=0,
-                      literal_termination=0, level_charge=0)
+                      literal_termination=0, level_charge=0, simple=0)
 
 
 class _OgResult(ctypes.Structure):

@@ -93,6 +93,10 @@ typedef struct {
     /* added to alpha * n + m per level of the last global relabel's
      * breadth-first search (0 in the paper's rule) */
     int64_t level_charge;
+    /* 1: the simple synchronous rounds that Sec. 3 describes first (one
+     * pass over the arcs, pushes on every admissible arc with no win
+     * criterion, at most one relabel); 0: Listing 1's rounds */
+    int64_t simple;
 } og_sched;
 
 int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,

@@ -24,6 +24,14 @@
  *    global relabel run at that point finds none (see prsn_phase);
  *  - the global relabel follows residual arcs w -> v, i.e. tests
  *    c_f(w,v) > 0, which is what a BFS in the reverse residual graph needs.
+ *
+ * With og_sched.simple the rounds are those of the simple synchronous
+ * algorithm Sec. 3 describes before its improvements: each active vertex
+ * checks its arcs once, pushing on every admissible arc (no win criterion),
+ * and if it still holds excess takes one new label, computed from the
+ * round-start labels of the heads of its residual arcs with d(w) >= d(v)
+ * (the candidates Listing 1 uses, so that a label never decreases).  Labels
+ * and excess changes apply at the round's end, as in the other rounds.
  */
 #include <stdlib.h>
 #include <string.h>
@@ -153,7 +161,7 @@ static int prsn_phase(sync_state *S, int64_t sink, int64_t other, int64_t max_ro
                     if (e == 0) break;               /* discharged completely */
                     int64_t w = g->head[a];
                     int admissible = (S->dprime[v] == S->d[w] + 1);
-                    if (S->e[w] != 0) {              /* edge shared by two active vertices */
+                    if (S->e[w] != 0 && !sc->simple) {   /* edge shared by two active vertices */
                         int win = (S->d[v] == S->d[w] + 1) || (S->d[v] < S->d[w] - 1) ||
                                   (S->d[v] == S->d[w] && v < w);
                         if (admissible && !win) { skipped = 1; continue; }
@@ -182,6 +190,7 @@ static int prsn_phase(sync_state *S, int64_t sink, int64_t other, int64_t max_ro
                 S->work[v] += outDegree + beta;
                 S->relabels++;
                 if (S->dprime[v] == n) break;
+                if (sc->simple) break;               /* simple rounds: one pass, one relabel */
             }
             S->addedExcess[v] += e - S->e[v];
             touch_vertex(S, v);
@@ -229,7 +238,7 @@ int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,
 {
     int rc = og_validate(g);
     if (rc) return rc;
-    og_sched sc = {1, 2, 6, 12, 0, 0, 0};
+    og_sched sc = {1, 2, 6, 12, 0, 0, 0, 0};
     if (sched) sc = *sched;
     if (sc.freq_den <= 0 || sc.freq_num < 0 || sc.alpha < 0 || sc.beta < 0 || sc.round_charge < 0 ||
         sc.level_charge < 0)

@@ -23,6 +23,7 @@ MF_PREFLOW_ONLY = 0x1
 MF_PROFILE = 0x2
 MF_PERSISTENT = 0x4
 MF_GRID_PATH = 0x8
+MF_SIMPLE_ROUNDS = 0x10
 
 
 class MaxflowError(RuntimeError):
@@ -155,6 +156,8 @@ def options(**kw) -> mf_options:
             o.flags = (o.flags | MF_PERSISTENT) if v else (o.flags & ~MF_PERSISTENT)
         elif k == "grid_path":
             o.flags = (o.flags | MF_GRID_PATH) if v else (o.flags & ~MF_GRID_PATH)
+        elif k == "simple_rounds":
+            o.flags = (o.flags | MF_SIMPLE_ROUNDS) if v else (o.flags & ~MF_SIMPLE_ROUNDS)
         else:
             setattr(o, k, int(v))
     return o

@@ -697,10 +697,9 @@ __global__ void k_read_value(const int64_t *e, int t, Ctl *ctl) { ctl->value = e
         else hipLaunchKernelGGL(K, dim3(GRID), dim3(256), 0, S, __VA_ARGS__);                         \
     } while (0)
 
-void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int hubd, int grid,
-                      hipStream_t s, KEv ev)
+void launch_discharge(int G, bool dense, GraphView g, StateView st, RoundParams p, int grid, hipStream_t s,
+                      KEv ev)
 {
-    RoundParams p{beta, sink, hubd};
 #define C_(X)                                                      \
     if (dense) MF_LAUNCH((k_discharge_dense<X>), grid, s, ev, g, st, p); \
     else MF_LAUNCH((k_discharge_list<X>), grid, s, ev, g, st, p)
@@ -718,10 +717,9 @@ void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int ot
 #undef C_
 }
 
-void launch_discharge_hubs(bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid, hipStream_t s,
-                           KEv ev)
+void launch_discharge_hubs(bool dense, GraphView g, StateView st, RoundParams p, int grid, hipStream_t s, KEv ev)
 {
-    RoundParams p{beta, sink};
+    p.hubd = 0x7fffffff;
     if (dense) MF_LAUNCH(k_discharge_hubs<true>, grid, s, ev, g, st, p);
     else MF_LAUNCH(k_discharge_hubs<false>, grid, s, ev, g, st, p);
 }

@@ -54,6 +54,17 @@ struct Ctl {
     int64_t td_slots;      // profiling: slots expanded by the top-down levels of a relabel
 };
 
+// Parameters of a discharge step (host-built, passed to the kernels by value).
+struct RoundParams {
+    int64_t beta;      // work per relabel = outdeg + beta
+    int sink;          // pushes into the sink go straight to its reverse slot and excess
+    int hubd = 0x7fffffff;   // vertices of higher degree are left to a block each (hub kernels)
+    // The simple synchronous variant of Sec. 3 (the paper's first design):
+    // every admissible arc is used, with no win criterion, and an active
+    // vertex makes one pass over its arcs and at most one relabel per round.
+    int simple = 0;
+};
+
 // Per-solve state.  Every array lives in device memory.
 //   res[a]    residual capacity of slot a as of the last round end
 //   delta[a]  push received on slot a during the current round (a push on

@@ -36,6 +36,7 @@ struct PhaseParams {
     int64_t freq_num, freq_den, alpha, beta, round_charge, level_charge, max_rounds;
     int64_t dense_threshold, bu_factor;
     int hubdeg;
+    int simple;              // rounds of the simple synchronous variant (RoundParams::simple)
     uint64_t limit_ticks;    // grid-barrier wait limit in wall-clock ticks
 };
 

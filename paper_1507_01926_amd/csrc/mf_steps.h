@@ -5,12 +5,6 @@
 
 namespace mf {
 
-struct RoundParams {
-    int64_t beta;      // work per relabel = outdeg + beta
-    int sink;          // pushes into the sink go straight to its reverse slot and excess
-    int hubd = 0x7fffffff;   // vertices of higher degree are left to a block each (hub kernels)
-};
-
 // One pass over a chunk of up to G slots, in slot order.  Each lane holds one
 // slot: r its residual, w its head, dw = d(w), aw = act(w).  Pushes along
 // admissible arcs the vertex may use take min(r, e - excl) where excl is the
@@ -24,11 +18,11 @@ template <int G, bool DENSE>
 __device__ __forceinline__ int chunk_pass(const GraphView &g, StateView &st, int v, int dv, int dp,
                                           int gl, int a, int &r, int w, int dw, bool aw,
                                           int64_t &el, bool &lose, int64_t &pushes, int sink,
-                                          int64_t &to_sink)
+                                          int64_t &to_sink, bool simple)
 {
     const bool adm = r > 0 && dp == dw + 1;
     const bool win = (dv == dw + 1) || (dv < dw - 1) || (dv == dw && v < w);
-    lose = adm && aw && !win;
+    lose = !simple && adm && aw && !win;
     const bool use = adm && !lose;
     const int64_t amt = use ? (int64_t)r : 0;
     const int64_t incl = group_incl_scan<G>(amt, gl);
@@ -97,7 +91,7 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
             if (gl == 0) acc.scans += deg;
             bool lose;
             if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, acc.pushes, p.sink,
-                                     acc.to_sink) > 0)
+                                     acc.to_sink, p.simple) > 0)
                 dirty = true;
             if (el == 0) break;
             const int cand = (r > 0 && dw >= dp) ? dw + 1 : n;
@@ -109,6 +103,7 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
                 acc.relabels++;
             }
             if (dp >= n) break;
+            if (p.simple) break;                              // one relabel per round
         }
         if (dirty) st.res[a] = r;
     } else {
@@ -130,7 +125,7 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
                 if (gl == 0) acc.scans += (end - base) < G ? (end - base) : G;
                 bool lose;
                 if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, acc.pushes, p.sink,
-                                         acc.to_sink) > 0)
+                                         acc.to_sink, p.simple) > 0)
                     st.res[a] = r;
                 if (el == 0) break;
                 if (r > 0 && dw >= dp && dw + 1 < cand) cand = dw + 1;
@@ -145,6 +140,7 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
                 acc.relabels++;
             }
             if (dp >= n) break;
+            if (p.simple) break;
         }
     }
     if (gl == 0) {
@@ -309,7 +305,7 @@ __device__ __forceinline__ void discharge_hub(const GraphView &g, StateView &st,
             if (tid == 0) acc.scans += (end - base) < HUB_BLOCK ? (end - base) : HUB_BLOCK;
             const bool adm = r > 0 && dp == dw + 1;
             const bool win = (dv == dw + 1) || (dv < dw - 1) || (dv == dw && v < w);
-            const bool lose = adm && aw && !win;
+            const bool lose = !p.simple && adm && aw && !win;
             const bool use = adm && !lose;
             const int64_t amt = use ? (int64_t)r : 0;
             int64_t tot;
@@ -352,6 +348,7 @@ __device__ __forceinline__ void discharge_hub(const GraphView &g, StateView &st,
             acc.relabels++;
         }
         if (dp >= n) break;
+        if (p.simple) break;
     }
     if (tid == 0) {
         st.dn[v] = dp;

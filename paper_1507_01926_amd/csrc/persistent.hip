@@ -109,7 +109,7 @@ __device__ int run_phase_team(Team &tm, Stage &stage, const GraphView &g, const 
     const int wave = gtid >> 6;
     const int nwaves = gthreads >> 6;
     const int sink = P.sink, other = P.other;
-    const RoundParams rp{P.beta, sink};
+    const RoundParams rp{P.beta, sink, 0x7fffffff, P.simple};
 
     int64_t W = 0;
     int64_t depth = 0;           // depth of the last global relabel

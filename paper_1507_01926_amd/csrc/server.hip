@@ -536,6 +536,7 @@ static bool admit(mf_server *sv, Request *r)
     it.p.dense_threshold = o.dense_threshold > 0 ? o.dense_threshold : std::max<int64_t>(512, r->n / 16);
     it.p.bu_factor = o.bfs_bottom_up_factor > 0 ? o.bfs_bottom_up_factor : 8;
     it.p.hubdeg = 64 * r->G;
+    it.p.simple = (o.flags & MF_SIMPLE_ROUNDS) ? 1 : 0;
     it.ctl = (Ctl *)(base + L.end);
     r->index = index;
     sv->slot_owner[q][index % SERVE_CAP] = r;

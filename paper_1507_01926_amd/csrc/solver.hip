@@ -29,12 +29,12 @@
 #include "mf_host.h"
 
 namespace mf {
-void launch_discharge_hubs(bool dense, GraphView g, StateView st, int64_t beta, int sink, int grid, hipStream_t s,
+void launch_discharge_hubs(bool dense, GraphView g, StateView st, RoundParams p, int grid, hipStream_t s,
                            KEv ev = KEv());
 void launch_merge_hubs(bool dense, GraphView g, StateView st, int sink, int other, int grid, hipStream_t s,
                        KEv ev = KEv());
-void launch_discharge(int G, bool dense, GraphView g, StateView st, int64_t beta, int sink, int hubd, int grid,
-                      hipStream_t s, KEv ev = KEv());
+void launch_discharge(int G, bool dense, GraphView g, StateView st, RoundParams p, int grid, hipStream_t s,
+                      KEv ev = KEv());
 void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int hubd, int grid,
                   hipStream_t s, KEv ev = KEv());
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
@@ -718,6 +718,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
     mf_context *ctx = S.ctx;
     const int64_t n = S.g.n, m = S.g.slots;
     const mf_options &o = S.opt;
+    const RoundParams rp{o.gr_beta, sink, S.hubd, (o.flags & MF_SIMPLE_ROUNDS) ? 1 : 0};
     bool force = true;
     int64_t W = 0;
     int na = 0;
@@ -764,10 +765,10 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                 const hipEvent_t *e = ctx->lev.data();
                 const int q = 8 * j;
                 if (j == 0) launch_round_begin(ctx->ctl, 1, ctx->stream);
-                launch_discharge(S.G, false, S.g, sj, o.gr_beta, sink, S.hubd, dgrid, ctx->stream,
+                launch_discharge(S.G, false, S.g, sj, rp, dgrid, ctx->stream,
                        kev(S, MF_K_DISCHARGE_LIST, e, q + 0));
                 if (S.hub_kernels) {
-                    launch_discharge_hubs(false, S.g, sj, o.gr_beta, sink, S.hub_grid, ctx->stream,
+                    launch_discharge_hubs(false, S.g, sj, rp, S.hub_grid, ctx->stream,
                            kev(S, MF_K_DISCHARGE_HUB, e, q + 2));
                 }
                 launch_merge(S.Gm, false, S.g, sj, sink, other, S.hubd, mgrid, ctx->stream,
@@ -848,11 +849,11 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             launch_compact_flags(S.st.act, (int)n, S.st.A, &ctx->ctl->na, S.maxgrid, ctx->stream,
                    kev(S, MF_K_COMPACT, e, 0));
         }
-        launch_discharge(S.G, true, S.g, S.st, o.gr_beta, sink, S.hubd, grid_for(na, groups, S.maxgrid),
+        launch_discharge(S.G, true, S.g, S.st, rp, grid_for(na, groups, S.maxgrid),
                          ctx->stream,
                kev(S, MF_K_DISCHARGE_DENSE, e, 2));
         if (S.hub_kernels) {
-            launch_discharge_hubs(true, S.g, S.st, o.gr_beta, sink, S.hub_grid, ctx->stream,
+            launch_discharge_hubs(true, S.g, S.st, rp, S.hub_grid, ctx->stream,
                    kev(S, MF_K_DISCHARGE_HUB, e, 4));
         }
         launch_compact_flags(S.st.touched, (int)n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream,
@@ -919,6 +920,7 @@ static mf_status run_phase_persistent(Solve &S, int sink, int other, int64_t max
     P.dense_threshold = S.dense_threshold;
     P.bu_factor = S.bu_factor;
     P.hubdeg = 64 * S.G;          // the phase kernel expands frontier vertices with G lanes
+    P.simple = (o.flags & MF_SIMPLE_ROUNDS) ? 1 : 0;
     P.limit_ticks = ctx->wall_hz * 30ull;      // 30 s: far above any single step
     int per_cu = phase_blocks_per_cu(S.G);
     if (per_cu <= 0) return fail(ctx, MF_EDEVICE, "occupancy query for the persistent kernel failed");
@@ -1029,6 +1031,7 @@ static mf_status solve_small(mf_context *ctx, mf_dgraph *dg, const mf_options &o
     P.dense_threshold = o.dense_threshold > 0 ? o.dense_threshold : std::max<int64_t>(512, dg->n / 16);
     P.bu_factor = o.bfs_bottom_up_factor > 0 ? o.bfs_bottom_up_factor : 8;
     P.hubdeg = 64 * it.G;
+    P.simple = (o.flags & MF_SIMPLE_ROUNDS) ? 1 : 0;
     P.limit_ticks = 0;
     BatchQueue &q = *(BatchQueue *)(host.data() + oq);
     q.next = 0;
@@ -1417,6 +1420,7 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
         P.dense_threshold = oi.dense_threshold > 0 ? oi.dense_threshold : std::max<int64_t>(512, gh.n / 16);
         P.bu_factor = oi.bfs_bottom_up_factor > 0 ? oi.bfs_bottom_up_factor : 8;
         P.hubdeg = 64 * it.G;
+        P.simple = (oi.flags & MF_SIMPLE_ROUNDS) ? 1 : 0;
         P.limit_ticks = 0;
         it.preflow_only = (oi.flags & MF_PREFLOW_ONLY) ? 1 : 0;
         results[i].lanes_per_vertex = it.G;

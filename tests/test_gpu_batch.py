@@ -59,8 +59,9 @@ def test_batch_schedules_and_stream_instances(ctx):
     for i, g in enumerate(graphs):
         rc = (12 * g.n + 2 * g.slots) // [0, 16, 128][i % 3] if i % 3 else 0
         lc = [0, 5000, 50000][(i // 3) % 3]
-        opts.append(mf.options(gr_round_charge=rc, gr_level_charge=lc))
-        scheds.append(dict(round_charge=rc, level_charge=lc))
+        simple = i % 4 == 3
+        opts.append(mf.options(gr_round_charge=rc, gr_level_charge=lc, simple_rounds=simple))
+        scheds.append(dict(round_charge=rc, level_charge=lc, simple=int(simple)))
     res, _ = mf.batch_solve(ctx, graphs, opts=opts)
     for g, r, sc in zip(graphs, res, scheds):
         _check_one(g, r, sc)

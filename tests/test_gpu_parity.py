@@ -38,8 +38,10 @@ def _note(msg):
 def _compare(ctx, g, sched=None, lanes=0, check_a=True, **extra):
     import paper_1507_01926_amd as mf
     sched = dict(sched or {})
-    opt = mf.options(lanes_per_vertex=lanes, **extra, **{("gr_" + k if not k.startswith("gr_") else k): v
-                                                          for k, v in sched.items()})
+    gpu_sched = {("gr_" + k if not k.startswith("gr_") else k): v for k, v in sched.items() if k != "simple"}
+    if sched.get("simple"):
+        gpu_sched["simple_rounds"] = True
+    opt = mf.options(lanes_per_vertex=lanes, **extra, **gpu_sched)
     osched = {k.replace("gr_", "").replace("freq_num", "freq_num"): v for k, v in sched.items()}
     r = ctx.solve(g, opt)
     B = oracle.sync_maxflow(g, schedule=osched)
@@ -116,6 +118,28 @@ def test_schedules(ctx, sched):
     g = make_config("c3", 8)
     _note(f"schedule {sched}")
     _compare(ctx, g, sched=sched, check_a=False)
+
+
+@pytest.mark.parametrize("name,f,lanes", [("c1", 1, 0), ("c2", 16, 0), ("c2", 64, 8), ("c3", 8, 0),
+                                           ("c4a", 32, 0), ("c4b", 16, 0), ("c4b", 16, 32)])
+def test_simple_rounds_match_oracle(ctx, name, f, lanes):
+    """The simple synchronous variant of Sec. 3 (MF_SIMPLE_ROUNDS) against the
+    oracle run with the same rounds: value, T*, per-slot flow and counts."""
+    g = make_config(name, f)
+    _note(f"simple rounds {name}/{f} lanes={lanes}")
+    _compare(ctx, g, sched=dict(simple=1, round_charge=(12 * g.n + 2 * g.slots) // 128), lanes=lanes)
+    if g.n <= 8192:
+        _compare(ctx, g, sched=dict(simple=1), lanes=lanes, grid_path=True, check_a=False)
+    _compare(ctx, g, sched=dict(simple=1), persistent=True, check_a=False)
+
+
+@pytest.mark.parametrize("grid_path", [False, True])
+def test_simple_rounds_random_small_graphs(ctx, grid_path):
+    for seed in range(300, 340):
+        n = 4 + seed % 30
+        g = random_graph(n, (2 + seed % 5) * n, seed, cap_max=50)
+        _note(f"simple rounds random seed={seed} n={n} grid_path={grid_path}")
+        _compare(ctx, g, sched=dict(simple=1), lanes=[0, 1, 2, 8, 64][seed % 5], grid_path=grid_path)
 
 
 @pytest.mark.parametrize("k", [1, 2, 7, 30])

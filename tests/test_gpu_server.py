@@ -47,6 +47,25 @@ def test_server_mix_equals_alone_and_oracle(ctx):
         assert r["ms_latency"] > 0
 
 
+def test_server_simple_rounds_requests(ctx):
+    """Requests that ask for the simple synchronous rounds of Sec. 3, mixed
+    with requests for Listing 1's rounds: each equals the oracle run with the
+    same rounds."""
+    import paper_1507_01926_amd as mf
+    srv = mf.Server(ctx, hbm_budget_bytes=1 << 30)
+    graphs = [stream_instance(i, n_hi=2e4) for i in range(12)]
+    simple = [i % 2 == 0 for i in range(len(graphs))]
+    tickets = [srv.submit(g, mf.options(simple_rounds=s)) for g, s in zip(graphs, simple)]
+    results = [srv.wait(t, 120000) for t in tickets]
+    srv.close()
+    for g, s, r in zip(graphs, simple, results):
+        assert r is not None and r["status"] == 0
+        B = oracle.sync_maxflow(g, schedule=dict(simple=int(s)))
+        assert r["value"] == B["value"] and (r["sink_side"] == B["tstar"]).all()
+        assert (r["flow"].astype(np.int64) == B["flow"]).all()
+        assert r["rounds"] == B["rounds"] and r["rounds2"] == B["rounds2"]
+
+
 def test_server_budget_admission_and_rejections(ctx):
     import paper_1507_01926_amd as mf
     budget = 24 << 20

@@ -240,6 +240,48 @@ def test_schedules_change_rounds_not_results():
     assert len(grs) > 2          # the schedules do change how often the labels are recomputed
 
 
+# ---------------------------------------------------------------- simple rounds
+
+def test_simple_rounds_one_pass_and_one_relabel():
+    """The simple synchronous variant Sec. 3 starts from: in a round each
+    active vertex checks its arcs once and relabels at most once.  In c1's
+    first round the 64 active vertices are the left column, each with
+    excess 1000 and one admissible arc (to its right neighbour, capacity at
+    most 100): one push and one relabel each.  Listing 1's full discharge
+    goes on pushing after the relabel."""
+    g = make_config("c1")
+    S = oracle.sync_maxflow(g, preflow_only=True, max_rounds=1, schedule=dict(simple=1))
+    B = oracle.sync_maxflow(g, preflow_only=True, max_rounds=1)
+    assert S["rounds"] == 1 and S["pushes"] == 64 and S["relabels"] == 64
+    assert B["pushes"] > 64
+
+
+@pytest.mark.parametrize("chunk", range(2))
+def test_simple_rounds_brute_force(chunk):
+    for seed in range(chunk * 50, chunk * 50 + 50):
+        n = 4 + seed % 14
+        g = random_graph(n, (2 + seed % 4) * n, seed)
+        best, tstar, smin = brute_mincut(g)
+        S = oracle.sync_maxflow(g, schedule=dict(simple=1))
+        assert S["value"] == best, seed
+        assert (S["tstar"] == tstar).all(), seed
+        _cert_ok(g, S["flow"], S["tstar"])
+
+
+@pytest.mark.parametrize("name,f", [("c1", 1), ("c2", 16), ("c3", 8), ("c4a", 32), ("c4b", 16)])
+def test_simple_rounds_families(name, f):
+    """Same maximum and sink side as the FIFO oracle; more rounds than
+    Listing 1's rounds on every family but the shallow R-MAT."""
+    g = make_config(name, f)
+    A = oracle.fifo_maxflow(g, preflow_only=True)
+    S = oracle.sync_maxflow(g, schedule=dict(simple=1))
+    B = oracle.sync_maxflow(g)
+    assert S["value"] == A["value"] == B["value"]
+    assert (S["tstar"] == A["tstar"]).all()
+    _cert_ok(g, S["flow"], S["tstar"])
+    assert S["rounds"] >= B["rounds"]
+
+
 def test_certificate_rejects_non_maximum_and_invalid():
     g = path_graph([4, 2, 6])
     A = oracle.fifo_maxflow(g)
