@@ -208,6 +208,9 @@ def main():
                     help="use the paper's global-relabel rule without the per-round charge")
     ap.add_argument("--simple-rounds", action="store_true",
                     help="rounds of the simple synchronous variant of Sec. 3 (ablation of Listing 1's rounds)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the global-relabel schedule with the autotuner (timed plain solves of this "
+                         "graph before the warm-up) instead of the default rule")
     ap.add_argument("--level-charge", type=int, default=0,
                     help="global-relabel threshold charge per level of the last relabel's search")
     ap.add_argument("--stream", type=int, default=256,
@@ -234,6 +237,15 @@ def main():
     dev = torch.device("cuda:0")
     flow = torch.empty(max(1, g.slots), dtype=torch.int32, device=dev)
     side = torch.empty(g.n, dtype=torch.uint8, device=dev)
+    tuned = None
+    if args.autotune:
+        from paper_1507_01926_amd.autotune import Autotuner
+        print("[bench] autotuning the global-relabel schedule", file=sys.stderr, flush=True)
+        tuned = Autotuner(ctx, cache_path=None).tune_schedule(dg, g, reps=2)
+        k = tuned["knobs"]
+        thr = 12 * g.n + 2 * g.slots
+        sched = dict(gr_round_charge=max(1, thr // k["round_divisor"]), gr_freq_num=1,
+                     gr_freq_den=k["freq_den"], gr_level_charge=k["level_charge"])
     opt = mf.options(profile=True, persistent=args.persistent, simple_rounds=args.simple_rounds, **sched)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
@@ -304,6 +316,7 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "n": g.n, "arcs": g.m_arcs, "slots": g.slots,
                    "schedule": sched or "paper (freq 1/2, alpha 6, beta 12)",
+                   "schedule_from": "autotuner (timed plain solves of this graph)" if tuned else "fixed rule",
                    "rounds": "simple synchronous variant (Sec. 3)" if args.simple_rounds
                              else "Listing 1 (win criterion, full discharge)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -13,6 +13,14 @@ path but not the maximum-flow value, cut or sink side):
   dense_divisor      rounds with more than n/dense_divisor active vertices walk
                      all vertices instead of a list (the degree/size
                      threshold between the two layouts)
+  freq_den           the global-relabel frequency of the work rule (Sec. 3):
+                     a relabel runs when W > freq_den * (alpha*n + m)
+                     (2 = the paper's 1/2)
+  level_charge       charge per breadth-first level of the last relabel
+                     added to the threshold (0 = the paper's rule)
+
+`tune_schedule` searches the last four for one plain solve (the lane and
+dense knobs keep their automatic values there).
 
 Instances are bucketed by (floor(log2 n), round(log2 average degree),
 whether the maximum degree exceeds 64x the average).  For each bucket the
@@ -45,13 +53,20 @@ def bucket_of(g) -> str:
     return f"n{int(math.log2(max(2, n)))}-d{int(round(math.log2(max(1.0, avg))))}-h{int(hub)}"
 
 
+# Global-relabel schedules tried by tune_schedule: (round_divisor, freq_den,
+# level_charge).  The first is the benchmark's default rule.
+SCHEDULES = ((128, 2, 0), (64, 4, 0), (128, 8, 0), (32, 1, 0), (16, 1, 0), (128, 2, 1 << 17))
+
+
 def knobs_to_options(g, knobs: dict, **extra):
     thr = 12 * int(g.n) + 2 * int(g.head.shape[0])
     rd = int(knobs.get("round_divisor", 0))
     dd = int(knobs.get("dense_divisor", 0))
     return options(lanes_per_vertex=int(knobs.get("lanes_per_vertex", 0)),
                    gr_round_charge=(thr // rd) if rd else 0,
-                   dense_threshold=max(1, int(g.n) // dd) if dd else 0, **extra)
+                   dense_threshold=max(1, int(g.n) // dd) if dd else 0,
+                   gr_freq_num=1, gr_freq_den=int(knobs.get("freq_den", 2)),
+                   gr_level_charge=int(knobs.get("level_charge", 0)), **extra)
 
 
 class Autotuner:
@@ -100,6 +115,24 @@ class Autotuner:
             dt = 1e3 * (time.perf_counter() - t0)
             best = dt if best is None else min(best, dt)
         return best
+
+    def tune_schedule(self, dg, g, reps: int = 2, schedules=SCHEDULES, verbose: bool = False) -> dict:
+        """Time the global-relabel schedules on one uploaded graph (plain
+        solves through the C ABI) and cache the fastest for its bucket under
+        "schedule:<bucket>".  Returns the cache entry."""
+        timings = []
+        for rd, fd, lc in schedules:
+            knobs = dict(lanes_per_vertex=0, dense_divisor=0, round_divisor=rd, freq_den=fd, level_charge=lc)
+            timings.append((self._time_plain(dg, g, knobs, reps), knobs))
+            if verbose:
+                print(f"[autotune] schedule {knobs}: {timings[-1][0]:.2f} ms", flush=True)
+        timings.sort(key=lambda x: x[0])
+        ms, best = timings[0]
+        entry = {"knobs": best, "ms": ms, "samples": 1,
+                 "candidates": [{"ms": t, "knobs": c} for t, c in timings]}
+        self.cache[f"schedule:{bucket_of(g)}"] = entry
+        self.save()
+        return entry
 
     def tune(self, graphs, mode: str = "plain", reps: int = 2, lanes=LANES, round_divisors=ROUND_DIVISORS,
              dense_divisors=DENSE_DIVISORS, verbose: bool = False) -> dict:

@@ -86,3 +86,24 @@ def test_batch_equals_plain_solver(ctx):
         p = ctx.solve(g)
         assert p["value"] == r["value"] and (p["flow"] == r["flow"]).all()
         assert (p["sink_side"] == r["sink_side"]).all() and p["rounds"] == r["rounds"]
+
+
+def test_schedule_autotuner_plain(ctx):
+    """The autotuner's schedule search on one uploaded graph: every
+    candidate is timed, and the schedule it picks gives the oracle's
+    results run with that schedule."""
+    from paper_1507_01926_amd.autotune import Autotuner, SCHEDULES, knobs_to_options
+    g = make_config("c2", 16)
+    dg = ctx.upload(g)
+    try:
+        entry = Autotuner(ctx, cache_path=None).tune_schedule(dg, g, reps=1)
+        assert len(entry["candidates"]) == len(SCHEDULES)
+        k = entry["knobs"]
+        r = dg.solve(knobs_to_options(g, k))
+        B = oracle.sync_maxflow(g, schedule=dict(round_charge=(12 * g.n + 2 * g.slots) // k["round_divisor"],
+                                                 freq_num=1, freq_den=k["freq_den"],
+                                                 level_charge=k["level_charge"]))
+        assert r["value"] == B["value"] and r["cut_capacity"] == B["value"]
+        assert r["rounds"] == B["rounds"] and r["global_relabels"] == B["global_relabels"]
+    finally:
+        dg.free()
