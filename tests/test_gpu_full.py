@@ -54,3 +54,46 @@ def test_full_size_workload(name):
     code, val, cut = oracle.check_certificate(g, r["flow"].astype(np.int64), r["sink_side"])
     assert code == 0, oracle.CERT_CODES[code]
     assert val == cut == gold["value"]
+
+
+_GRAPHS = {}
+
+
+def _graph(name):
+    if name not in _GRAPHS:
+        _GRAPHS.clear()
+        _GRAPHS[name] = make_config(name)
+    return _GRAPHS[name]
+
+
+def _schedule_cases():
+    from paper_1507_01926_amd.autotune import SCHEDULES
+    cases = []
+    for name in NAMES:
+        for sc in SCHEDULES[1:]:
+            if name in ("c3", "c4a") and sc[2] == 0:
+                continue                    # deep-search graphs: the level-charge schedule only
+            cases.append((name, sc))
+    return cases
+
+
+@pytest.mark.parametrize("name,sched", _schedule_cases())
+def test_full_size_other_schedules(name, sched):
+    """The schedules the benchmark's autotuner chooses among change rounds and
+    per-slot flow, never the value, the cut or the sink side."""
+    import paper_1507_01926_amd as mf
+    from paper_1507_01926_amd.autotune import knobs_to_options
+    gold = json.load(open(os.path.join(GOLDEN, f"full_{name}.json")))
+    g = _graph(name)
+    rd, fd, lc = sched
+    print(f"full-size {name}: schedule {sched}", flush=True)
+    ctx = mf.Context(0)
+    try:
+        r = ctx.solve(g, knobs_to_options(g, dict(round_divisor=rd, freq_den=fd, level_charge=lc)))
+    finally:
+        ctx.close()
+    sys.stdout.flush()
+    assert r["value"] == gold["value"] and r["cut_capacity"] == gold["cut"]
+    assert _sha(r["sink_side"].astype(np.uint8)) == gold["tstar_sha256"]
+    code, val, cut = oracle.check_certificate(g, r["flow"].astype(np.int64), r["sink_side"])
+    assert code == 0, oracle.CERT_CODES[code]
