@@ -247,7 +247,7 @@ def main():
     if not (args.fixed_schedule or args.paper_schedule):
         from paper_1507_01926_amd.autotune import Autotuner
         print("[bench] autotuning the global-relabel schedule", file=sys.stderr, flush=True)
-        tuned = Autotuner(ctx, cache_path=None).tune_schedule(dg, g, reps=2)
+        tuned = Autotuner(ctx, cache_path=None).tune_schedule(dg, g, reps=2, verbose=True)
         k = tuned["knobs"]
         thr = 12 * g.n + 2 * g.slots
         sched = dict(gr_round_charge=max(1, thr // k["round_divisor"]), gr_freq_num=1,

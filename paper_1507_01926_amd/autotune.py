@@ -33,6 +33,7 @@ import itertools
 import json
 import math
 import os
+import sys
 import time
 
 import numpy as np
@@ -125,7 +126,7 @@ class Autotuner:
             knobs = dict(lanes_per_vertex=0, dense_divisor=0, round_divisor=rd, freq_den=fd, level_charge=lc)
             timings.append((self._time_plain(dg, g, knobs, reps), knobs))
             if verbose:
-                print(f"[autotune] schedule {knobs}: {timings[-1][0]:.2f} ms", flush=True)
+                print(f"[autotune] schedule {knobs}: {timings[-1][0]:.2f} ms", file=sys.stderr, flush=True)
         timings.sort(key=lambda x: x[0])
         ms, best = timings[0]
         entry = {"knobs": best, "ms": ms, "samples": 1,
