@@ -97,6 +97,13 @@ typedef struct {
                                   labels apply at the round's end as in the default rounds.  Value,
                                   cut and sink side are the same; rounds, pushes and per-slot flow
                                   differ */
+#define MF_WARM_START   0x20u  /* resume from the flow of the last complete solve of this graph on
+                                  this context, after mf_graph_set_caps changed its capacities
+                                  (see there): the residual state stays on the device and the
+                                  solve pushes only the flow the changes allow.  Value, cut and
+                                  sink side are those of the new graph.  MF_EINVAL if the context
+                                  holds no resumable state for the graph.  Uses the grid-wide
+                                  kernels whatever the graph's size */
 #define MF_SMALL_N      8192
 #define MF_SMALL_SLOTS  16384
 
@@ -218,6 +225,21 @@ void mf_context_destroy(mf_context *ctx);
  * invalid graph, MF_ENOMEM beyond the budget. */
 mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_dgraph **out);
 void mf_graph_free(mf_context *ctx, mf_dgraph *dg);
+
+/* Replaces the capacities of an uploaded graph (the structure stays):
+ * cap[slots] is a host array (on_device = 0) or a device array
+ * (on_device = 1), checked as at upload (cap >= 0, pair sums below 2^31);
+ * MF_EINVAL leaves the graph unchanged.  For re-solving a graph whose
+ * capacities change between solves (vision and partitioning workloads,
+ * Sec. 4 of the paper): if the context's last solve was a complete solve of
+ * this graph by the grid-wide kernels (graphs small enough for the
+ * one-workgroup solve need MF_GRID_PATH for it), its flow is kept on the
+ * device, and a slot's residual moves by the capacity change.  *resumable (may be NULL) is then 1 if every new
+ * capacity is at least the slot's flow, so that a solve with MF_WARM_START
+ * can continue from that flow; otherwise 0, and the next solve starts from
+ * zero flow. */
+mf_status mf_graph_set_caps(mf_context *ctx, mf_dgraph *dg, const int32_t *cap, int on_device,
+                            int *resumable);
 
 /* Solves an uploaded graph on the context's stream.  flow_dev (int32[slots])
  * and side_dev (uint8[n]) are device pointers that receive the outputs, or

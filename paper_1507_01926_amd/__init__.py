@@ -24,6 +24,7 @@ MF_PROFILE = 0x2
 MF_PERSISTENT = 0x4
 MF_GRID_PATH = 0x8
 MF_SIMPLE_ROUNDS = 0x10
+MF_WARM_START = 0x20
 
 
 class MaxflowError(RuntimeError):
@@ -102,6 +103,7 @@ SIGNATURES = [
     ("mf_context_destroy", None, [_P]),
     ("mf_graph_upload", ctypes.c_int, [_P, _P, ctypes.c_int, _P]),
     ("mf_graph_free", None, [_P, _P]),
+    ("mf_graph_set_caps", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     ("mf_solve_uploaded", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve_device", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
@@ -158,6 +160,8 @@ def options(**kw) -> mf_options:
             o.flags = (o.flags | MF_GRID_PATH) if v else (o.flags & ~MF_GRID_PATH)
         elif k == "simple_rounds":
             o.flags = (o.flags | MF_SIMPLE_ROUNDS) if v else (o.flags & ~MF_SIMPLE_ROUNDS)
+        elif k == "warm_start":
+            o.flags = (o.flags | MF_WARM_START) if v else (o.flags & ~MF_WARM_START)
         else:
             setattr(o, k, int(v))
     return o
@@ -312,6 +316,16 @@ class DeviceGraph:
             self.free()
         except Exception:
             pass
+
+    def set_caps(self, cap) -> bool:
+        """mf_graph_set_caps from a host array of int32[slots]; returns whether
+        the next solve can resume from the kept flow (MF_WARM_START)."""
+        c = np.ascontiguousarray(cap, dtype=np.int32)
+        if c.shape[0] != self.slots:
+            raise ValueError("cap must have one entry per slot")
+        res = ctypes.c_int(0)
+        self.ctx._check(lib().mf_graph_set_caps(self.ctx.h, self.h, c.ctypes.data, 0, ctypes.byref(res)))
+        return bool(res.value)
 
     def solve(self, opt: mf_options | None = None, flow_ptr=None, side_ptr=None,
               allow_timeout=False) -> dict:

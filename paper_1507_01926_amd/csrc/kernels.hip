@@ -127,12 +127,48 @@ __global__ void k_init_state(GraphView g, StateView st)
 // Saturation of the arcs out of s, written like a dense round: the heads
 // receive the capacity in delta[] of the reverse slot and are marked touched;
 // an arc into t goes straight to t (see chunk_pass).
+// Saturates the arcs out of s: pushes each one's residual (its capacity
+// after k_init_state, what the last flow left of it after k_warm_state).
+// Start of a solve that resumes from the flow of the last complete solve:
+// the residuals stay, and so does e(t) (the value so far); every other
+// vertex had zero excess at the end of that solve.  Labels, flags and
+// deltas start as in k_init_state.
+__global__ void k_warm_state(GraphView g, StateView st)
+{
+    const int stride = gridDim.x * blockDim.x;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int a = tid; a < g.slots; a += stride) st.delta[a] = 0;
+    for (int v = tid; v < g.n; v += stride) {
+        const int lab = v == g.s ? g.n : 0;
+        st.d[v] = lab;
+        st.dn[v] = lab;
+        if (v != g.t) st.e[v] = 0;
+        st.act[v] = 0;
+        st.touched[v] = 0;
+    }
+}
+
+// New capacities of an uploaded graph; with `warm` the residuals of the kept
+// flow move by the same amounts, and a slot whose new capacity is below its
+// flow sets bit 128 of ctl->err.
+__global__ void k_recap(GraphView g, const int32_t *__restrict__ cap_new, int32_t *res, int warm, Ctl *ctl)
+{
+    int bad = 0;
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < g.slots; a += gridDim.x * blockDim.x) {
+        if (!warm) continue;
+        const int64_t r = (int64_t)res[a] + cap_new[a] - g.cap[a];
+        if (r < 0) bad = 1;
+        res[a] = (int32_t)(r < 0 ? 0 : r);
+    }
+    if (bad) atomicOr(&ctl->err, 128);
+}
+
 __global__ void k_saturate(GraphView g, StateView st)
 {
     const int beg = g.off[g.s], end = g.off[g.s + 1];
     int64_t to_sink = 0;
     for (int a = beg + blockIdx.x * blockDim.x + threadIdx.x; a < end; a += gridDim.x * blockDim.x) {
-        const int c = g.cap[a];
+        const int c = st.res[a];
         if (c <= 0) continue;
         const int w = g.head[a];
         st.res[a] = 0;
@@ -780,6 +816,14 @@ void launch_init_state(GraphView g, StateView st, int grid, hipStream_t s)
 void launch_saturate(GraphView g, StateView st, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_saturate, dim3(grid), dim3(256), 0, s, g, st);
+}
+void launch_warm_state(GraphView g, StateView st, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_warm_state, dim3(grid), dim3(256), 0, s, g, st);
+}
+void launch_recap(GraphView g, const int32_t *cap_new, int32_t *res, int warm, Ctl *ctl, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_recap, dim3(grid), dim3(256), 0, s, g, cap_new, res, warm, ctl);
 }
 void launch_gr_init(GraphView g, StateView st, int sink, int grid, hipStream_t s)
 {

@@ -63,6 +63,10 @@ struct mf_context {
     std::vector<hipEvent_t> lev;     // profiling of batched levels, created on first use
     Workspace ws;
     uint8_t *one = nullptr;    // device: item, result, queue and order of a single-workgroup solve
+    // the graph whose complete flow the workspace holds (residuals, excess
+    // of t), from the last grid-path solve; nullptr once anything else has
+    // used the workspace
+    const mf_dgraph *warm_dg = nullptr;
     int num_cus = 256;
     std::string err;
 };

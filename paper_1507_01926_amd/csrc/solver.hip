@@ -46,6 +46,8 @@ void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int
 void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s);
 void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s,
                           KEv ev = KEv());
+void launch_warm_state(GraphView g, StateView st, int grid, hipStream_t s);
+void launch_recap(GraphView g, const int32_t *cap_new, int32_t *res, int warm, Ctl *ctl, int grid, hipStream_t s);
 void launch_degree_stats(GraphView g, Ctl *ctl, int grid, hipStream_t s);
 void launch_round_begin(Ctl *ctl, int first, hipStream_t s);
 void launch_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num, int64_t freq_den,
@@ -315,6 +317,7 @@ extern "C" mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_
 extern "C" void mf_graph_free(mf_context *ctx, mf_dgraph *dg)
 {
     if (!dg) return;
+    if (ctx && ctx->warm_dg == dg) ctx->warm_dg = nullptr;
     if (ctx) {
         (void)hipSetDevice(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
@@ -325,6 +328,65 @@ extern "C" void mf_graph_free(mf_context *ctx, mf_dgraph *dg)
         dfree(ctx, dg->cap, 4 * S);
     }
     delete dg;
+}
+
+extern "C" mf_status mf_graph_set_caps(mf_context *ctx, mf_dgraph *dg, const int32_t *cap, int on_device,
+                                       int *resumable)
+{
+    if (resumable) *resumable = 0;
+    if (!ctx || !dg || (!cap && dg->slots > 0)) return fail(ctx, MF_EINVAL, "NULL argument");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t S = dg->slots;
+    if (S == 0) {
+        if (resumable) *resumable = ctx->warm_dg == dg;
+        return MF_OK;
+    }
+    int32_t *tmp = nullptr;
+    mf_status st = dalloc(ctx, (void **)&tmp, 4 * S);
+    if (st != MF_OK) return st;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(ctx->stream);
+        dfree(ctx, tmp, 4 * S);
+    };
+    hipError_t he = hipMemcpyAsync(tmp, cap, 4 * S, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                   ctx->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream);
+    if (he != hipSuccess) {
+        release();
+        return fail(ctx, MF_EDEVICE, "capacity upload failed: %s", hipGetErrorString(he));
+    }
+    const int maxg = ctx->num_cus * 8;
+    GraphView gv = dg->view();
+    gv.cap = tmp;
+    launch_validate(gv, ctx->ctl, grid_for(S, 256, maxg), ctx->stream);
+    if ((st = read_ctl(ctx)) != MF_OK) {
+        release();
+        return st;
+    }
+    if (ctx->ctl_host->err) {
+        const int bits = ctx->ctl_host->err;
+        release();
+        return fail(ctx, MF_EINVAL, "invalid capacities: %s", validation_message(bits));
+    }
+    // the kept flow moves with the capacities (its residuals change by the
+    // same amounts); then the new capacities replace the old ones
+    const bool warm = ctx->warm_dg == dg;
+    launch_recap(dg->view(), tmp, ctx->ws.res, warm ? 1 : 0, ctx->ctl, grid_for(S, 256, maxg), ctx->stream);
+    he = hipMemcpyAsync(dg->cap, tmp, 4 * S, hipMemcpyDeviceToDevice, ctx->stream);
+    if (he != hipSuccess) {
+        release();
+        ctx->warm_dg = nullptr;
+        return fail(ctx, MF_EDEVICE, "capacity update failed: %s", hipGetErrorString(he));
+    }
+    st = read_ctl(ctx);
+    release();
+    if (st != MF_OK) {
+        ctx->warm_dg = nullptr;
+        return st;
+    }
+    if (warm && (ctx->ctl_host->err & 128)) ctx->warm_dg = nullptr;   // a flow above its new capacity
+    if (resumable) *resumable = ctx->warm_dg == dg;
+    return MF_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1087,9 +1149,16 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     if (st != MF_OK) return st;
     const bool preflow_only = (o.flags & MF_PREFLOW_ONLY) != 0;
     if (preflow_only && flow_dev) return fail(ctx, MF_EINVAL, "flow output requires phase 2");
+    const bool warm = (o.flags & MF_WARM_START) != 0;
+    if (warm && ctx->warm_dg != dg)
+        return fail(ctx, MF_EINVAL, "no resumable flow of this graph on this context (MF_WARM_START needs a "
+                                    "complete solve of it as the context's last solve, and capacities that "
+                                    "still hold its flow)");
+    ctx->warm_dg = nullptr;       // the workspace is about to change
     HIPCHK(ctx, hipSetDevice(ctx->device));
     if ((st = ensure_workspace(ctx, dg->n, dg->slots)) != MF_OK) return st;
-    if (!(o.flags & (MF_PERSISTENT | MF_GRID_PATH)) && dg->n <= MF_SMALL_N && dg->slots <= MF_SMALL_SLOTS)
+    if (!warm && !(o.flags & (MF_PERSISTENT | MF_GRID_PATH)) && dg->n <= MF_SMALL_N &&
+        dg->slots <= MF_SMALL_SLOTS)
         return solve_small(ctx, dg, o, value, flow_dev, side_dev, stats);
 
     Solve S;
@@ -1141,7 +1210,10 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     const int n = dg->n;
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
-    launch_init_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
+    if (warm)
+        launch_warm_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
+    else
+        launch_init_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
     launch_saturate(S.g, S.st, ctx->num_cus * 4, ctx->stream);
     launch_compact_flags(S.st.touched, n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream);
     launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, S.hubd, grid_for(n, 256 / S.Gm, S.maxgrid), ctx->stream);
@@ -1178,6 +1250,8 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
     if ((st = read_ctl(ctx)) != MF_OK) return st;
     HIPCHK(ctx, hipGetLastError());
+    // a complete flow stays in the workspace for a resumed solve
+    if (!preflow_only && !timed_out) ctx->warm_dg = dg;
 
     if (value) *value = val;
     if (stats) {
