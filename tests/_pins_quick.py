@@ -15,6 +15,10 @@ from workloads import random_graph              # noqa: E402
 from tests._graphs import graph_from_json, path_graph   # noqa: E402
 
 
+def full_value(g):
+    return oracle.fifo_maxflow(g, preflow_only=True)["value"]
+
+
 def main():
     try:
         for seed in range(40):
@@ -38,6 +42,18 @@ def main():
             return 1
         full = oracle.sync_maxflow(g)
         if full["flow"].tolist() != gold["phase2"]["flow"]:
+            return 1
+        # simple rounds (Sec. 3's first design): c1's first round is one push
+        # and one relabel for each of its 64 active vertices
+        from workloads import make_config
+        c1 = make_config("c1")
+        s1 = oracle.sync_maxflow(c1, preflow_only=True, max_rounds=1, schedule=dict(simple=1))
+        if (s1["pushes"], s1["relabels"]) != (64, 64):
+            return 1
+        # the per-level charge (a schedule term) changes when labels are
+        # recomputed, never the value
+        lv = oracle.sync_maxflow(c1, schedule=dict(level_charge=100000))
+        if lv["value"] != full_value(c1) or lv["global_relabels"] == oracle.sync_maxflow(c1)["global_relabels"]:
             return 1
     except Exception:
         return 1

@@ -21,6 +21,9 @@ MUTANTS = [
     ("sync.c", "S->addedExcess[v] += e - S->e[v];", "S->addedExcess[v] = e - S->e[v];"), # listing's '='
     ("sync.c", "if (S->res[a] > 0 && S->d[w] >= S->dprime[v]) {",
      "if (S->res[a] > 0 && S->d[w] > S->dprime[v]) {"),                                  # relabel candidate bound
+    ("sync.c", "if (sc->simple) break;               /* simple rounds: one pass, one relabel */",
+     "(void)0;"),                                                                        # simple: full discharge
+    ("sync.c", "lastDepth = GlobalRelabel(S, sink, other);", "GlobalRelabel(S, sink, other);"),  # level charge dropped
     ("fifo.c", "S->res[g->rev[a]] += delta;", "(void)delta;"),                           # lost reverse residual
     ("fifo.c", "nd = S->d[g->head[a]] + 1;", "nd = S->d[g->head[a]];"),                  # relabel off by one
     ("fifo.c", "if (S->res[a] > 0 && S->d[v] == S->d[w] + 1) {",
