@@ -4,6 +4,7 @@ CPU only."""
 import ctypes
 import os
 import re
+import sys
 
 import pytest
 
@@ -108,3 +109,32 @@ def test_autotuner_buckets_and_defaults(tmp_path):
     assert again.knobs_for(g1)["lanes_per_vertex"] == 16
     o = again.options_for(g1)
     assert o.lanes_per_vertex == 16 and o.gr_round_charge == (12 * g1.n + 2 * g1.slots) // 32
+
+
+def test_schedule_knobs_and_mode_flags_map_to_options():
+    """The autotuner's schedule knobs and the mode keywords of options()
+    land in the fields and flags the header defines (host logic)."""
+    import paper_1507_01926_amd as mf
+    from paper_1507_01926_amd import autotune
+    from workloads import make_config
+    g = make_config("c1")
+    thr = 12 * g.n + 2 * g.slots
+    for rd, fd, lc in autotune.SCHEDULES:
+        o = autotune.knobs_to_options(g, dict(round_divisor=rd, freq_den=fd, level_charge=lc))
+        assert (o.gr_round_charge, o.gr_freq_num, o.gr_freq_den, o.gr_level_charge) == (thr // rd, 1, fd, lc)
+    assert autotune.SCHEDULES[0] == (128, 2, 0)          # the benchmark's fixed rule comes first
+    o = mf.options(simple_rounds=True, warm_start=True, grid_path=True)
+    assert o.flags == mf.MF_SIMPLE_ROUNDS | mf.MF_WARM_START | mf.MF_GRID_PATH
+    o = mf.options(simple_rounds=False)
+    assert o.flags & mf.MF_SIMPLE_ROUNDS == 0
+    header = open(os.path.join(ROOT, "include", "maxflow.h")).read()
+    for name, val in (("MF_SIMPLE_ROUNDS", mf.MF_SIMPLE_ROUNDS), ("MF_WARM_START", mf.MF_WARM_START),
+                      ("MF_GRID_PATH", mf.MF_GRID_PATH)):
+        assert f"#define {name}" in header and hex(val) in header.split(f"#define {name}")[1].split("u")[0]
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
