@@ -464,6 +464,7 @@ __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView s
 template <int G>
 __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView st, RoundParams p)
 {
+    if (st.ctl->batch_stop) return;
     const int na = st.ctl->na;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
@@ -515,6 +516,7 @@ __global__ __launch_bounds__(256) void k_merge_list(GraphView g, StateView st, i
 template <int G>
 __global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, int sink, int other, int hubd)
 {
+    if (st.ctl->batch_stop) return;
     const int nc = st.ctl->nc;
     const int gl = threadIdx.x & (G - 1);
     const int groups = blockDim.x / G;
@@ -539,8 +541,10 @@ __global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, 
 // places the entries and one atomic per block reserves their range.
 // flags must be 16-byte aligned.
 __global__ __launch_bounds__(256) void k_compact_flags(const uint8_t *__restrict__ flags, int n,
-                                                      int32_t *__restrict__ list, int32_t *count)
+                                                      int32_t *__restrict__ list, int32_t *count,
+                                                      const int32_t *stop)
 {
+    if (stop && *stop) return;          // a later round of a stopped batch
     __shared__ int s_wave[4];
     __shared__ int s_base;
     const int nchunks = (n + 15) >> 4;
@@ -662,15 +666,18 @@ __global__ void k_round_begin(Ctl *ctl, int first)
     ctl->nhm = 0;
 }
 
+// dense: a batch of dense rounds, which stops instead when the next working
+// set is small enough for a list round (or empty).
 __global__ void k_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num,
-                              int64_t freq_den, int64_t gr_threshold, int64_t dense_threshold)
+                              int64_t freq_den, int64_t gr_threshold, int64_t dense_threshold, int dense)
 {
     if (ctl->batch_stop) return;
     const int64_t W = (first ? W0 : ctl->batch_W) + ctl->work + charge;
     ctl->batch_W = W;
-    ctl->batch_rounds++;
+    ctl->batch_rounds = first ? 1 : ctl->batch_rounds + 1;
     const int64_t next = ctl->na2;
-    if (next == 0 || next > dense_threshold || freq_num * W > freq_den * gr_threshold) {
+    const bool other_kind = dense ? next <= dense_threshold : (next == 0 || next > dense_threshold);
+    if (other_kind || freq_num * W > freq_den * gr_threshold) {
         ctl->batch_stop = 1;
         return;
     }
@@ -788,13 +795,13 @@ void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int 
     hipLaunchKernelGGL(k_gr_collect, dim3(grid), dim3(256), 0, s, g, st, level, qout);
 }
 void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s,
-                          KEv ev)
+                          KEv ev, const int32_t *stop)
 {
     const int chunks = (n + 15) / 16;
     int grid = (chunks + 255) / 256;
     if (grid > maxgrid) grid = maxgrid;
     if (grid < 1) grid = 1;
-    MF_LAUNCH(k_compact_flags, grid, s, ev, flags, n, list, count);
+    MF_LAUNCH(k_compact_flags, grid, s, ev, flags, n, list, count, stop);
 }
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s)
@@ -851,10 +858,10 @@ void launch_round_begin(Ctl *ctl, int first, hipStream_t s)
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, s, ctl, first);
 }
 void launch_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num, int64_t freq_den,
-                        int64_t gr_threshold, int64_t dense_threshold, hipStream_t s)
+                        int64_t gr_threshold, int64_t dense_threshold, hipStream_t s, int dense)
 {
     hipLaunchKernelGGL(k_round_close, dim3(1), dim3(1), 0, s, ctl, first, W0, charge, freq_num, freq_den,
-                       gr_threshold, dense_threshold);
+                       gr_threshold, dense_threshold, dense);
 }
 void launch_side(GraphView g, const int32_t *d, uint8_t *side, int grid, hipStream_t s)
 {

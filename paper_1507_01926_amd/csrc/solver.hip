@@ -45,13 +45,13 @@ void launch_gr_bu(GraphView g, StateView st, int level, int sink, int other, int
                   KEv ev = KEv());
 void launch_gr_collect(GraphView g, StateView st, int level, int32_t *qout, int grid, hipStream_t s);
 void launch_compact_flags(const uint8_t *flags, int n, int32_t *list, int32_t *count, int maxgrid, hipStream_t s,
-                          KEv ev = KEv());
+                          KEv ev = KEv(), const int32_t *stop = nullptr);
 void launch_warm_state(GraphView g, StateView st, int grid, hipStream_t s);
 void launch_recap(GraphView g, const int32_t *cap_new, int32_t *res, int warm, Ctl *ctl, int grid, hipStream_t s);
 void launch_degree_stats(GraphView g, Ctl *ctl, int grid, hipStream_t s);
 void launch_round_begin(Ctl *ctl, int first, hipStream_t s);
 void launch_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, int64_t freq_num, int64_t freq_den,
-                        int64_t gr_threshold, int64_t dense_threshold, hipStream_t s);
+                        int64_t gr_threshold, int64_t dense_threshold, hipStream_t s, int dense = 0);
 void launch_narrow(const int64_t *off64, const int64_t *rev64, int32_t *off, int32_t *rev, int32_t n,
                    int64_t slots, Ctl *ctl, int grid, hipStream_t s);
 void launch_validate(GraphView g, Ctl *ctl, int grid, hipStream_t s);
@@ -786,6 +786,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
     int na = 0;
     bool dense = false;
     int rbatch = 1;              // list rounds per readback: doubles up to 16 while no round stops a batch
+    int dbatch = 1;              // dense rounds per readback: doubles up to 8 likewise
     bool list_ready = false;     // the working set is listed in A (else only flagged in act)
     while (true) {
         bool just = false;
@@ -893,71 +894,106 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             na = count;
             continue;
         }
-        // Dense round: the working set as a list (the previous round's merge
-        // wrote it; after a global relabel it is listed from the activity
-        // flags), discharge the listed vertices, list the touched vertices,
-        // merge them.
+        // Dense rounds, speculatively batched like the list rounds: up to
+        // `dbatch` rounds with one readback.  Each round: the working set as
+        // a list (the previous round's merge wrote it; after a global relabel
+        // it is listed from the activity flags), discharge of the listed
+        // vertices, list of the touched vertices, their merge, and a
+        // one-thread close that stops the batch when the next round must not
+        // be a dense round (working set at or below the dense threshold) or
+        // W calls for a global relabel.  Every kernel of a later round then
+        // returns at once.
         rbatch = 1;
+        int K = dbatch;
+        if (max_rounds > 0) K = (int)std::min<int64_t>(K, max_rounds - ps.rounds);
         launch_round_reset(ctx->ctl, !list_ready, ctx->stream);
         const int groups = 256 / S.G;
+        const int64_t na_room = K == 1 ? (int64_t)na : 2 * (int64_t)na;      // later rounds may grow
+        const int dgrid = grid_for(na_room, groups, S.maxgrid);
+        const int mgrid = grid_for(std::min<int64_t>(n, na_room * (1 + S.avg_deg_ceil)), 256 / S.Gm, S.maxgrid);
         if (S.profile) {
-            mf_status est = batch_events(ctx, 12);
+            mf_status est = batch_events(ctx, 12 * 8);
             if (est != MF_OK) return est;
         }
-        // events bracket: compaction of the working set, discharge, hub
-        // discharge, compaction of the touched vertices, merge, hub merge
-        const hipEvent_t *e = ctx->lev.data();
-        if (!list_ready) {
-            launch_compact_flags(S.st.act, (int)n, S.st.A, &ctx->ctl->na, S.maxgrid, ctx->stream,
-                   kev(S, MF_K_COMPACT, e, 0));
-        }
-        launch_discharge(S.G, true, S.g, S.st, rp, grid_for(na, groups, S.maxgrid),
-                         ctx->stream,
-               kev(S, MF_K_DISCHARGE_DENSE, e, 2));
-        if (S.hub_kernels) {
-            launch_discharge_hubs(true, S.g, S.st, rp, S.hub_grid, ctx->stream,
-                   kev(S, MF_K_DISCHARGE_HUB, e, 4));
-        }
-        launch_compact_flags(S.st.touched, (int)n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream,
-               kev(S, MF_K_COMPACT, e, 6));
-        const int64_t cand_items = std::min<int64_t>(n, (int64_t)na * (1 + S.avg_deg_ceil));
-        launch_merge(S.Gm, true, S.g, S.st, sink, other, S.hubd, grid_for(cand_items, 256 / S.Gm, S.maxgrid),
-                     ctx->stream,
-               kev(S, MF_K_MERGE_DENSE, e, 8));
-        if (S.hub_kernels) {
-            launch_merge_hubs(true, S.g, S.st, sink, other, S.hub_grid, ctx->stream,
-                   kev(S, MF_K_MERGE_HUB, e, 10));
+        // events 12j .. 12j+11 bracket round j's compaction of the working
+        // set, discharge, hub discharge, compaction of the touched vertices,
+        // merge and hub merge
+        const bool compact_first = !list_ready;
+        StateView sj = S.st;
+        for (int j = 0; j < K; j++) {
+            const hipEvent_t *e = ctx->lev.data() + 12 * j;
+            if (j == 0 && compact_first) {
+                launch_compact_flags(sj.act, (int)n, sj.A, &ctx->ctl->na, S.maxgrid, ctx->stream,
+                       kev(S, MF_K_COMPACT, e, 0));
+            }
+            launch_discharge(S.G, true, S.g, sj, rp, dgrid, ctx->stream,
+                   kev(S, MF_K_DISCHARGE_DENSE, e, 2));
+            if (S.hub_kernels) {
+                launch_discharge_hubs(true, S.g, sj, rp, S.hub_grid, ctx->stream,
+                       kev(S, MF_K_DISCHARGE_HUB, e, 4));
+            }
+            launch_compact_flags(sj.touched, (int)n, sj.C, &ctx->ctl->nc, S.maxgrid, ctx->stream,
+                   kev(S, MF_K_COMPACT, e, 6), &ctx->ctl->batch_stop);
+            launch_merge(S.Gm, true, S.g, sj, sink, other, S.hubd, mgrid, ctx->stream,
+                   kev(S, MF_K_MERGE_DENSE, e, 8));
+            if (S.hub_kernels) {
+                launch_merge_hubs(true, S.g, sj, sink, other, S.hub_grid, ctx->stream,
+                       kev(S, MF_K_MERGE_HUB, e, 10));
+            }
+            launch_round_close(ctx->ctl, j == 0, W, o.gr_round_charge, o.gr_freq_num, o.gr_freq_den,
+                               o.gr_alpha * n + m + o.gr_level_charge * S.gr_depth, S.dense_threshold,
+                               ctx->stream, 1);
+            std::swap(sj.A, sj.A2);
         }
         mf_status st = read_ctl(ctx);
         if (st != MF_OK) return st;
+        const Ctl &c = *ctx->ctl_host;
+        const int r = c.batch_rounds;
+        const bool stopped = c.batch_stop != 0;
+        W = c.batch_W;
+        ps.rounds += r;
+        S.dense_rounds += r;
         if (S.profile) {
-            const Ctl &c = *ctx->ctl_host;
             int64_t b[4];
             round_bytes(S, c, b);
-            const double md = span(S, MF_K_DISCHARGE_DENSE, e, 2, 3), mm = span(S, MF_K_MERGE_DENSE, e, 8, 9);
-            S.ms_dis += timed_ms(md);
-            S.ms_mer += timed_ms(mm);
-            S.n_dis++;
-            S.n_mer++;
-            if (!list_ready) kernel_record(S, MF_K_COMPACT, span(S, MF_K_COMPACT, e, 0, 1), n + 4 * (int64_t)c.na);
-            kernel_record(S, MF_K_DISCHARGE_DENSE, md, b[0]);
-            kernel_record(S, MF_K_COMPACT, span(S, MF_K_COMPACT, e, 6, 7), n + 4 * (int64_t)c.nc);
-            kernel_record(S, MF_K_MERGE_DENSE, mm, b[2]);
-            if (S.hub_kernels) {
-                kernel_record(S, MF_K_DISCHARGE_HUB, span(S, MF_K_DISCHARGE_HUB, e, 4, 5), b[1]);
-                kernel_record(S, MF_K_MERGE_HUB, span(S, MF_K_MERGE_HUB, e, 10, 11), b[3]);
+            for (int j = 0; j < K; j++) {
+                const hipEvent_t *e = ctx->lev.data() + 12 * j;
+                const bool ran = j < r;       // rounds after the stop returned at once
+                const double md = span(S, MF_K_DISCHARGE_DENSE, e, 2, 3);
+                const double mm = span(S, MF_K_MERGE_DENSE, e, 8, 9);
+                S.ms_dis += timed_ms(md);
+                S.ms_mer += timed_ms(mm);
+                if (j == 0 && compact_first)
+                    kernel_record(S, MF_K_COMPACT, span(S, MF_K_COMPACT, e, 0, 1), n + 4 * (int64_t)na);
+                kernel_record(S, MF_K_DISCHARGE_DENSE, md, j == 0 ? b[0] : 0);
+                // the touched-list compaction reads n flags per round it ran
+                kernel_record(S, MF_K_COMPACT, span(S, MF_K_COMPACT, e, 6, 7), ran ? n : 0);
+                kernel_record(S, MF_K_MERGE_DENSE, mm, j == 0 ? b[2] : 0);
+                if (S.hub_kernels) {
+                    kernel_record(S, MF_K_DISCHARGE_HUB, span(S, MF_K_DISCHARGE_HUB, e, 4, 5), j == 0 ? b[1] : 0);
+                    kernel_record(S, MF_K_MERGE_HUB, span(S, MF_K_MERGE_HUB, e, 10, 11), j == 0 ? b[3] : 0);
+                }
             }
+            S.n_dis += K;
+            S.n_mer += K;
             S.last = c;
         }
-        S.dense_rounds++;
-        W += ctx->ctl_host->work + o.gr_round_charge;
-        const int count = ctx->ctl_host->na2;
-        dense = count > S.dense_threshold;
-        launch_round_end(ctx->ctl, ctx->stream);   // the merge listed the next working set: na = na2
-        std::swap(S.st.A, S.st.A2);
+        // the rounds the device closed each made the next working set current
+        if ((stopped ? r - 1 : r) & 1) std::swap(S.st.A, S.st.A2);
         list_ready = true;
+        if (!stopped) {
+            na = c.na;
+            dbatch = std::min(8, 2 * dbatch);
+            continue;
+        }
+        // the round that stopped the batch: its merge listed the next
+        // working set in A2
+        dbatch = 1;
+        const int count = c.na2;
+        dense = count > S.dense_threshold;
+        launch_round_end(ctx->ctl, ctx->stream);   // na = na2
+        std::swap(S.st.A, S.st.A2);
         na = count;
-        ps.rounds++;
     }
 }
 
