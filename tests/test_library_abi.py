@@ -138,3 +138,28 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_traffic_only_for_the_profiled_sources(monkeypatch):
+    """The benchmark reports the counter-measured traffic of the dominant
+    kernel only while the profile was taken on the current HIP sources."""
+    sys.path.insert(0, ROOT)
+    import bench
+    path = os.path.join(ROOT, "profiles", "k_gr_td_c2_traffic.txt")
+    recorded = [l.split(":", 1)[1].strip() for l in open(path) if l.startswith("source_sha256:")][0]
+    per_launch = [float(l.split(":", 1)[1]) for l in open(path) if l.startswith("hbm_bytes_per_launch:")][0]
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: recorded)
+    assert bench.measured_traffic("k_gr_td", "c2") == per_launch
+    assert bench.measured_traffic("k_gr_td", "c3") is None     # no profile for that workload
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 64)
+    assert bench.measured_traffic("k_gr_td", "c2") is None     # sources changed since the counters
+
+
+def test_bench_fixed_schedule():
+    sys.path.insert(0, ROOT)
+    import bench
+    from workloads import make_config
+    g = make_config("c1")
+    thr = 12 * g.n + 2 * g.slots
+    assert bench.fixed_schedule(g) == {"gr_round_charge": thr // 128}
+    assert bench.fixed_schedule(g, 1 << 17) == {"gr_round_charge": thr // 128, "gr_level_charge": 1 << 17}
