@@ -6,9 +6,10 @@ with the HIP library and never imports it.
 
 * ``fifo_maxflow``  oracle A: sequential FIFO push-relabel (Sec. 2.1) with
   global relabeling every ~12n+2m units of relabel work (Sec. 3), int64.
-* ``sync_maxflow``  oracle B: the paper's synchronous rounds (Sec. 3.1,
-  Listing 1) with level-synchronous global relabeling (Listing 2), executed
-  sequentially; each round is a function of its start state.
+* ``sync_maxflow``  oracle B: the paper's synchronous rounds (Sec. 3.1)
+  with global relabeling by a breadth-first search from the sink (Sec. 2.1,
+  Sec. 3), executed sequentially; each round is a function of its start
+  state.
 * ``check_certificate``  max-flow / min-cut certificate (Sec. 2, Eq. 1-2).
 * ``brute_mincut`` (in ``brute``)  enumeration of every s-t cut.
 """
@@ -33,17 +34,18 @@ class _OgGraph(ctypes.Structure):
 class _OgSched(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "freq_num", "freq_den", "alpha", "beta", "round_charge", "literal_termination",
-        "level_charge", "simple")]
+        "level_charge", "simple", "gap")]
 
 
 PAPER_SCHEDULE = dict(freq_num=1, freq_den=2, alpha=6, beta=12, round_charge=0,
-                      literal_termination=0, level_charge=0, simple=0)
+                      literal_termination=0, level_charge=0, simple=0, gap=0)
 
 
 class _OgResult(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "value", "cut_tstar", "cut_smin", "pushes", "relabels", "global_relabels", "rounds",
-        "pushes2", "relabels2", "global_relabels2", "rounds2", "work", "bfs_levels")]
+        "pushes2", "relabels2", "global_relabels2", "rounds2", "work", "bfs_levels",
+        "gap_lifts", "gap_lifts2")]
 
 
 def lib():

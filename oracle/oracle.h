@@ -44,6 +44,7 @@ typedef struct {
     int64_t pushes2, relabels2, global_relabels2, rounds2;   /* phase 2 */
     int64_t work;             /* sum of (out-degree + 12) over relabels, phase 1 */
     int64_t bfs_levels;       /* sum over global relabels of BFS depth, phase 1 */
+    int64_t gap_lifts, gap_lifts2;  /* oracle B with the gap rule: labels set to n by it */
 } og_result;
 
 /*
@@ -61,7 +62,7 @@ int og_fifo_maxflow(const og_graph *g, int preflow_only, int64_t *res_out,
 
 /*
  * Oracle B: the synchronous parallel push-relabel rounds of the paper
- * (Sec. 3.1, Listing 1) with parallel global relabeling (Listing 2),
+ * (Sec. 3.1) with parallel global relabeling (Sec. 2.1, Sec. 3),
  * simulated one vertex at a time.  Every vertex of the working set is
  * discharged against the labels and excesses of the start of the round; a
  * push into a neighbour becomes visible in the neighbour's residual capacity
@@ -95,8 +96,13 @@ typedef struct {
     int64_t level_charge;
     /* 1: the simple synchronous rounds that Sec. 3 describes first (one
      * pass over the arcs, pushes on every admissible arc with no win
-     * criterion, at most one relabel); 0: Listing 1's rounds */
+     * criterion, at most one relabel); 0: the full discharges of Sec. 3.1 */
     int64_t simple;
+    /* 1: the gap rule at the end of every round (Sec. 3 names gap
+     * relabeling, after Cherkassky and Goldberg): when no vertex other than
+     * the terminals holds label k, 0 < k < n, every label in (k, n) becomes
+     * n, for the smallest such k */
+    int64_t gap;
 } og_sched;
 
 int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,

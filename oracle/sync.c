@@ -1,37 +1,54 @@
 /*
- * Oracle B: the paper's synchronous push-relabel (prsn, Sec. 3.1, Listing 1)
- * with its parallel global relabeling (Listing 2), executed one vertex at a
- * time in exact int64.  Test infrastructure only (see oracle.h).
+ * Oracle B: the synchronous push-relabel method of Sec. 3.1 with the
+ * parallel global relabel (a breadth-first search from the sink over the
+ * reverse residual graph, Sec. 2.1 and Sec. 3), computed one vertex at a
+ * time in exact int64 arithmetic.  Test infrastructure only (see oracle.h).
  *
- * Readings of points the pseudocode leaves open:
- *  - initial working set: the distinct heads of saturated source arcs other
- *    than s and t; the first iteration always runs a global relabel, which
- *    filters it;
- *  - parallel arcs out of s add their capacities to e(v);
- *  - "residual edge (v,w)" in the discharge means c_f(v,w) > 0 as v sees it;
- *    a neighbour's push into v becomes visible in v's residual capacities at
- *    the end of the round (the loser of an edge reads the capacity from
- *    before the winner's push, which the paper allows);
- *  - "if e(w)" tests the excess of w at the start of the round;
- *  - v.addedExcess accumulates (the listing's assignment would drop the
- *    neighbours' fetch-and-add contributions);
- *  - the test "e'(v)" means that v still holds excess after its discharge;
- *  - the filter of the new working set keeps the discovered vertices w with
- *    updated label d(w) < n, and the added excess of every vertex that
- *    received a push (t and filtered vertices included) is applied;
- *  - a global relabel rebuilds the working set from every vertex with
- *    positive excess and exact label below n, and the loop ends only when a
- *    global relabel run at that point finds none (see prsn_phase);
- *  - the global relabel follows residual arcs w -> v, i.e. tests
- *    c_f(w,v) > 0, which is what a BFS in the reverse residual graph needs.
+ * State between rounds: cf[a] (residual capacity of slot a), lab[v] (label)
+ * and exc[v] (excess).  A round is a pure function of that state:
  *
- * With og_sched.simple the rounds are those of the simple synchronous
- * algorithm Sec. 3 describes before its improvements: each active vertex
- * checks its arcs once, pushing on every admissible arc (no win criterion),
- * and if it still holds excess takes one new label, computed from the
- * round-start labels of the heads of its residual arcs with d(w) >= d(v)
- * (the candidates Listing 1 uses, so that a label never decreases).  Labels
- * and excess changes apply at the round's end, as in the other rounds.
+ *   discharge   every vertex of the working set, on its own, runs the full
+ *               discharge of Sec. 3.1: it walks its residual arcs in slot
+ *               order, pushing along each eligible arc (its raised label d'
+ *               is one more than the neighbour's label at the round start),
+ *               and raises d' when a walk ends with excess left, until the
+ *               excess is gone, d' reaches n, or it has to give way on an
+ *               eligible arc to an active neighbour that owns the edge (the
+ *               ownership rule of Sec. 3.1, decided on round-start labels).
+ *               Everything it reads about other vertices is round-start
+ *               state; its own residuals fall as it pushes.
+ *   round end   the pushes become visible to the heads: each push of x units
+ *               on slot a raises cf[rev a] by x and moves x units of excess
+ *               from tail to head; the raised labels replace the old ones.
+ *
+ * Deferring the reverse residuals to the round end is the reading of the race
+ * Sec. 3.1 allows (a vertex that gives way may see the residual capacity from
+ * before or after its neighbour's push; here always before).
+ *
+ * The working set of a round is the set of active vertices: neither
+ * terminal, positive excess, label below n.  After a global relabel it is
+ * rebuilt from all vertices (exact labels revive a vertex that an invalid
+ * label had parked at n), and the phase ends only when a global relabel run
+ * at that point finds no active vertex.  With sched->literal_termination the
+ * set is instead the previous one with its label-n vertices removed, and the
+ * phase ends as soon as that is empty (which can end early).
+ *
+ * A global relabel runs first and then whenever the relabel work since the
+ * last one crosses the rule of Sec. 3 (see og_sched).
+ *
+ * With sched->simple the rounds are those of the simple synchronous
+ * algorithm Sec. 3 starts from: one walk over the arcs with no ownership
+ * rule, then at most one raise of the label.
+ *
+ * With sched->gap the gap rule (Sec. 3 mentions gap relabeling and cites
+ * Cherkassky and Goldberg for it) runs at the end of every round: if no
+ * vertex other than the two terminals holds some label k with 0 < k < n,
+ * while some hold labels above k, none of those can reach the sink, and
+ * every label in (k, n) becomes n (k the smallest such gap).
+ *
+ * Phase 2 (flow reconstruction; the paper leaves the method open) runs the
+ * same rounds with s as the sink and t excluded, which returns every excess
+ * that cannot reach t to s.
  */
 #include <stdlib.h>
 #include <string.h>
@@ -40,195 +57,234 @@
 typedef struct {
     const og_graph *g;
     int64_t n, m;
-    int64_t *res;          /* residual capacity per slot as of the last round end    */
-    int64_t *pending;      /* pushes into the reverse slot, applied at round end     */
-    int64_t *d, *dprime, *e, *addedExcess, *work;
-    uint8_t *isDiscovered;
-    int64_t *workingSet, *next, nws;
-    int64_t *touchedSlots, ntouchedSlots;
-    int64_t *touchedVerts, ntouchedVerts;
-    uint8_t *vertTouched;
-    int64_t *Q, *Q2;
-    int64_t pushes, relabels, grs, rounds, work_total, levels;
-} sync_state;
+    int64_t *cf, *lab, *exc;      /* state between rounds                         */
+    /* round scratch */
+    int64_t *raised;              /* d' of each discharged vertex                 */
+    int64_t *change;              /* net excess change of each touched vertex     */
+    int64_t *back;                /* residual returned to each slot at round end  */
+    uint8_t *touched;             /* vertex pushed to or discharged this round    */
+    int64_t *tlist, nt;           /* the touched vertices                         */
+    int64_t *blist, nb;           /* slots with a nonzero back[]                  */
+    /* working set */
+    int64_t *ws, nws;
+    uint8_t *in_ws;
+    /* breadth-first search */
+    int64_t *fifo;
+    /* gap rule: number of non-terminal vertices per label below n */
+    int64_t *count;
+    /* tallies */
+    int64_t pushes, relabels, grs, rounds, work, levels, gap_lifts;
+} machine;
 
-/* Listing 2: level-synchronous BFS from the sink over the reverse residual
- * graph.  Returns its depth (the largest label it gives). */
-static int64_t GlobalRelabel(sync_state *S, int64_t sink, int64_t other)
+/* Exact distances to `sink` over residual arcs w -> v (cf of the reverse
+ * slot of v's slot toward w), never through `other`; n where there is no
+ * path.  Returns the largest distance given. */
+static int64_t bfs_labels(machine *M, int64_t sink, int64_t other)
 {
-    const og_graph *g = S->g;
-    int64_t n = S->n;
-    for (int64_t v = 0; v < n; v++) S->d[v] = n;
-    S->d[sink] = 0;
-    int64_t nq = 0;
-    S->Q[nq++] = sink;
-    int64_t level = 0;
-    while (nq > 0) {
-        int64_t nq2 = 0;
-        for (int64_t i = 0; i < nq; i++) {
-            int64_t v = S->Q[i];
-            for (int64_t a = g->off[v]; a < g->off[v + 1]; a++) {
-                int64_t w = g->head[a];
-                if (w == other) continue;
-                if (S->res[g->rev[a]] <= 0) continue;        /* c_f(w,v) > 0 */
-                if (w != sink && S->d[w] == n) {
-                    S->d[w] = S->d[v] + 1;
-                    S->Q2[nq2++] = w;
+    const og_graph *g = M->g;
+    const int64_t n = M->n;
+    for (int64_t v = 0; v < n; v++) M->lab[v] = n;
+    M->lab[sink] = 0;
+    int64_t head = 0, tail = 0, depth = 0;
+    M->fifo[tail++] = sink;
+    while (head < tail) {
+        const int64_t v = M->fifo[head++];
+        for (int64_t a = g->off[v]; a < g->off[v + 1]; a++) {
+            const int64_t w = g->head[a];
+            if (w == other || M->lab[w] != n) continue;
+            if (M->cf[g->rev[a]] > 0) {          /* w can send to v */
+                M->lab[w] = M->lab[v] + 1;
+                if (M->lab[w] > depth) depth = M->lab[w];
+                M->fifo[tail++] = w;
+            }
+        }
+    }
+    M->levels += depth;
+    M->grs++;
+    return depth;
+}
+
+/* Whether v, active, owns the edge to the active neighbour w (Sec. 3.1):
+ * v one level above w, or more than one level below it, or level with it and
+ * of smaller id.  Exactly one of v and w owns it. */
+static int owns_edge(int64_t dv, int64_t dw, int64_t v, int64_t w)
+{
+    return dv == dw + 1 || dv < dw - 1 || (dv == dw && v < w);
+}
+
+static void touch(machine *M, int64_t v)
+{
+    if (!M->touched[v]) {
+        M->touched[v] = 1;
+        M->tlist[M->nt++] = v;
+    }
+}
+
+static int active(const machine *M, int64_t v, int64_t sink, int64_t other)
+{
+    return v != sink && v != other && M->exc[v] > 0 && M->lab[v] < M->n;
+}
+
+/* Full discharge of v against the round-start state (see the file header).
+ * Round work: every raise of d' costs outdeg(v) + beta. */
+static void discharge(machine *M, int64_t v, int simple, int64_t beta)
+{
+    const og_graph *g = M->g;
+    const int64_t n = M->n, first = g->off[v], last = g->off[v + 1];
+    const int64_t d0 = M->lab[v];
+    int64_t dcur = d0;                /* d'(v) */
+    int64_t left = M->exc[v];
+    while (left > 0) {
+        int64_t lowest = n;           /* smallest d(w)+1 over residual arcs with d(w) >= d' */
+        int gave_way = 0;
+        for (int64_t a = first; a < last && left > 0; a++) {
+            if (M->cf[a] <= 0) continue;
+            const int64_t w = g->head[a];
+            const int64_t dw = M->lab[w];
+            if (dcur == dw + 1) {
+                if (!simple && M->exc[w] != 0 && !owns_edge(d0, dw, v, w)) {
+                    gave_way = 1;     /* w is active and owns the edge */
+                } else {
+                    const int64_t x = M->cf[a] < left ? M->cf[a] : left;
+                    M->cf[a] -= x;
+                    const int64_t b = g->rev[a];
+                    if (M->back[b] == 0) M->blist[M->nb++] = b;
+                    M->back[b] += x;
+                    M->change[w] += x;
+                    left -= x;
+                    touch(M, w);
+                    M->pushes++;
                 }
             }
+            if (M->cf[a] > 0 && dw >= dcur && dw + 1 < lowest) lowest = dw + 1;
         }
-        int64_t *tmp = S->Q; S->Q = S->Q2; S->Q2 = tmp;
-        nq = nq2;
-        if (nq) level++;
+        if (left == 0 || gave_way) break;
+        dcur = lowest;                /* <= n */
+        M->relabels++;
+        M->work += (last - first) + beta;
+        if (dcur == n || simple) break;
     }
-    S->levels += level;
-    S->grs++;
-    for (int64_t v = 0; v < n; v++) S->dprime[v] = S->d[v];
-    return level;
+    M->raised[v] = dcur;
+    M->change[v] += left - M->exc[v];
+    touch(M, v);
 }
 
-static void touch_vertex(sync_state *S, int64_t v)
+/* Labels below n held by non-terminal vertices, for the gap rule. */
+static void count_labels(machine *M, int64_t sink, int64_t other)
 {
-    if (!S->vertTouched[v]) {
-        S->vertTouched[v] = 1;
-        S->touchedVerts[S->ntouchedVerts++] = v;
+    memset(M->count, 0, sizeof(int64_t) * (size_t)M->n);
+    for (int64_t v = 0; v < M->n; v++)
+        if (v != sink && v != other && M->lab[v] < M->n) M->count[M->lab[v]]++;
+}
+
+/* Gap rule (file header).  The labels that lost a vertex this round are the
+ * only places a gap can open, since the rule leaves none behind; `lost`
+ * lists them (the old labels of the vertices that were raised). */
+static void apply_gap(machine *M, int64_t sink, int64_t other, const int64_t *lost, int64_t nlost)
+{
+    const int64_t n = M->n;
+    int64_t gap = n;
+    for (int64_t i = 0; i < nlost; i++)
+        if (lost[i] > 0 && lost[i] < gap && M->count[lost[i]] == 0) gap = lost[i];
+    if (gap == n) return;
+    for (int64_t v = 0; v < n; v++) {
+        if (v == sink || v == other) continue;
+        if (M->lab[v] > gap && M->lab[v] < n) {
+            M->count[M->lab[v]]--;
+            M->lab[v] = n;
+            M->gap_lifts++;
+        }
     }
 }
 
-/* Listing 1's main loop for one phase.  Returns 1 if max_rounds stopped it. */
-static int prsn_phase(sync_state *S, int64_t sink, int64_t other, int64_t max_rounds,
-                      const og_sched *sc)
+/* One phase toward `sink`.  Returns 1 if max_rounds stopped it. */
+static int run_phase(machine *M, int64_t sink, int64_t other, int64_t max_rounds, const og_sched *sc)
 {
-    const og_graph *g = S->g;
-    int64_t n = S->n;
-    const int64_t beta = sc->beta;
-    int grPending = 1;                     /* workSinceLastGR := infinity */
-    int64_t workSinceLastGR = 0;
-    int64_t lastDepth = 0;                 /* depth of the last global relabel */
-    int64_t rounds_here = 0;
+    const og_graph *g = M->g;
+    const int64_t n = M->n;
+    int must_relabel = 1;            /* the first step is a global relabel */
+    int64_t since = 0;               /* relabel work (and round charges) since the last one */
+    int64_t depth = 0;               /* depth of the last global relabel */
+    int64_t done = 0;                /* rounds of this phase */
+    int64_t *lost = M->fifo;         /* gap rule: old labels of raised vertices (the search is idle) */
     while (1) {
-        int justRelabeled = 0;
-        /* freq * workSinceLastGR > alpha * n + m (+ level_charge * depth of
-         * the last global relabel, 0 in the paper's rule) */
-        if (grPending || sc->freq_num * workSinceLastGR >
-                             sc->freq_den * (sc->alpha * n + S->m + sc->level_charge * lastDepth)) {
-            grPending = 0;
-            workSinceLastGR = 0;
-            lastDepth = GlobalRelabel(S, sink, other);
+        int fresh = 0;
+        if (must_relabel ||
+            sc->freq_num * since > sc->freq_den * (sc->alpha * n + M->m + sc->level_charge * depth)) {
+            depth = bfs_labels(M, sink, other);
+            since = 0;
+            must_relabel = 0;
+            fresh = 1;
+            int64_t k = 0;
             if (sc->literal_termination) {
-                int64_t k = 0;
-                for (int64_t i = 0; i < S->nws; i++)
-                    if (S->d[S->workingSet[i]] < n) S->workingSet[k++] = S->workingSet[i];
-                S->nws = k;
+                for (int64_t i = 0; i < M->nws; i++)
+                    if (M->lab[M->ws[i]] < n) M->ws[k++] = M->ws[i];
+                    else M->in_ws[M->ws[i]] = 0;
             } else {
-                /* Every vertex with excess and an exact label below n is
-                 * active again.  A loser that relabels past a winner pushing
-                 * into it can leave an invalid label behind (Sec. 3.1 allows
-                 * that case); the exact labels of the global relabel undo it,
-                 * and a vertex that the invalid label had pushed to n is taken
-                 * back in here. */
-                S->nws = 0;
+                for (int64_t i = 0; i < M->nws; i++) M->in_ws[M->ws[i]] = 0;
                 for (int64_t v = 0; v < n; v++)
-                    if (v != sink && v != other && S->e[v] > 0 && S->d[v] < n)
-                        S->workingSet[S->nws++] = v;
+                    if (active(M, v, sink, other)) {
+                        M->ws[k++] = v;
+                        M->in_ws[v] = 1;
+                    }
             }
-            justRelabeled = 1;
+            M->nws = k;
+            if (sc->gap) count_labels(M, sink, other);
         }
-        if (S->nws == 0) {
-            /* stop only when a fresh global relabel finds no active vertex */
-            if (justRelabeled || sc->literal_termination) return 0;
-            grPending = 1;
+        if (M->nws == 0) {
+            if (fresh || sc->literal_termination) return 0;
+            must_relabel = 1;        /* end only after a fresh relabel finds nothing */
             continue;
         }
-        if (max_rounds > 0 && rounds_here >= max_rounds) return 1;
-        rounds_here++;
-        S->rounds++;
+        if (max_rounds > 0 && done >= max_rounds) return 1;
+        done++;
+        M->rounds++;
 
-        int64_t nnext = 0;
-        S->ntouchedSlots = 0;
-        S->ntouchedVerts = 0;
-        for (int64_t i = 0; i < S->nws; i++) {
-            int64_t v = S->workingSet[i];
-            S->dprime[v] = S->d[v];
-            int64_t e = S->e[v];                 /* local copy */
-            S->work[v] = 0;
-            int64_t outDegree = g->off[v + 1] - g->off[v];
-            while (e > 0) {
-                int64_t newLabel = n;
-                int skipped = 0;
-                for (int64_t a = g->off[v]; a < g->off[v + 1]; a++) {
-                    if (S->res[a] <= 0) continue;    /* residual edges only */
-                    if (e == 0) break;               /* discharged completely */
-                    int64_t w = g->head[a];
-                    int admissible = (S->dprime[v] == S->d[w] + 1);
-                    if (S->e[w] != 0 && !sc->simple) {   /* edge shared by two active vertices */
-                        int win = (S->d[v] == S->d[w] + 1) || (S->d[v] < S->d[w] - 1) ||
-                                  (S->d[v] == S->d[w] && v < w);
-                        if (admissible && !win) { skipped = 1; continue; }
-                    }
-                    if (admissible && S->res[a] > 0) {
-                        int64_t delta = S->res[a] < e ? S->res[a] : e;
-                        S->res[a] -= delta;                  /* f(v,w) += delta */
-                        int64_t b = g->rev[a];
-                        if (S->pending[b] == 0) S->touchedSlots[S->ntouchedSlots++] = b;
-                        S->pending[b] += delta;              /* f(w,v) -= delta, seen at round end */
-                        e -= delta;
-                        S->addedExcess[w] += delta;
-                        touch_vertex(S, w);
-                        S->pushes++;
-                        if (w != sink && !S->isDiscovered[w]) {
-                            S->isDiscovered[w] = 1;
-                            S->next[nnext++] = w;
-                        }
-                    }
-                    if (S->res[a] > 0 && S->d[w] >= S->dprime[v]) {
-                        if (S->d[w] + 1 < newLabel) newLabel = S->d[w] + 1;
-                    }
+        /* discharge: every vertex of the working set against the round start */
+        const int64_t work_before = M->work;
+        M->nt = 0;
+        M->nb = 0;
+        for (int64_t i = 0; i < M->nws; i++) discharge(M, M->ws[i], (int)sc->simple, sc->beta);
+        since += M->work - work_before + sc->round_charge;
+
+        /* round end: labels, residuals returned to the heads, excesses */
+        int64_t nlost = 0;
+        for (int64_t i = 0; i < M->nws; i++) {
+            const int64_t v = M->ws[i];
+            if (M->raised[v] != M->lab[v]) {
+                if (sc->gap) {
+                    M->count[M->lab[v]]--;
+                    if (M->raised[v] < n) M->count[M->raised[v]]++;
+                    lost[nlost++] = M->lab[v];
                 }
-                if (e == 0 || skipped) break;
-                S->dprime[v] = newLabel;             /* relabel */
-                S->work[v] += outDegree + beta;
-                S->relabels++;
-                if (S->dprime[v] == n) break;
-                if (sc->simple) break;               /* simple rounds: one pass, one relabel */
-            }
-            S->addedExcess[v] += e - S->e[v];
-            touch_vertex(S, v);
-            if (e > 0 && !S->isDiscovered[v]) {
-                S->isDiscovered[v] = 1;
-                S->next[nnext++] = v;
+                M->lab[v] = M->raised[v];
             }
         }
+        for (int64_t i = 0; i < M->nb; i++) {
+            M->cf[M->blist[i]] += M->back[M->blist[i]];
+            M->back[M->blist[i]] = 0;
+        }
+        for (int64_t i = 0; i < M->nt; i++) {
+            const int64_t v = M->tlist[i];
+            M->exc[v] += M->change[v];
+            M->change[v] = 0;
+        }
+        if (sc->gap && nlost) apply_gap(M, sink, other, lost, nlost);
 
-        workSinceLastGR += sc->round_charge;
-        /* apply the new labels of the old working set and sum the work */
-        for (int64_t i = 0; i < S->nws; i++) {
-            int64_t v = S->workingSet[i];
-            S->d[v] = S->dprime[v];
-            workSinceLastGR += S->work[v];
-            S->work_total += S->work[v];
-        }
-        /* apply the excess changes and the deferred reverse residuals */
-        for (int64_t i = 0; i < S->ntouchedVerts; i++) {
-            int64_t v = S->touchedVerts[i];
-            S->e[v] += S->addedExcess[v];
-            S->addedExcess[v] = 0;
-            S->vertTouched[v] = 0;
-        }
-        for (int64_t i = 0; i < S->ntouchedSlots; i++) {
-            int64_t b = S->touchedSlots[i];
-            S->res[b] += S->pending[b];
-            S->pending[b] = 0;
-        }
-        /* new working set: discovered vertices whose label is below n */
+        /* next working set: the touched vertices that are active */
+        for (int64_t i = 0; i < M->nws; i++) M->in_ws[M->ws[i]] = 0;
         int64_t k = 0;
-        for (int64_t i = 0; i < nnext; i++) {
-            int64_t w = S->next[i];
-            S->isDiscovered[w] = 0;
-            if (S->d[w] < n) S->workingSet[k++] = w;
+        for (int64_t i = 0; i < M->nt; i++) {
+            const int64_t v = M->tlist[i];
+            M->touched[v] = 0;
+            if (active(M, v, sink, other)) {
+                M->ws[k++] = v;
+                M->in_ws[v] = 1;
+            }
         }
-        S->nws = k;
+        M->nws = k;
     }
+    (void)g;
 }
 
 int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,
@@ -238,70 +294,68 @@ int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,
 {
     int rc = og_validate(g);
     if (rc) return rc;
-    og_sched sc = {1, 2, 6, 12, 0, 0, 0, 0};
+    og_sched sc = {1, 2, 6, 12, 0, 0, 0, 0, 0};
     if (sched) sc = *sched;
     if (sc.freq_den <= 0 || sc.freq_num < 0 || sc.alpha < 0 || sc.beta < 0 || sc.round_charge < 0 ||
         sc.level_charge < 0)
         return OG_ESIZE;
-    int64_t n = g->n, M = g->slots > 0 ? g->slots : 1;
-    sync_state S;
-    memset(&S, 0, sizeof S);
-    S.g = g;
-    S.n = n;
-    S.m = g->slots;
-    S.res = (int64_t *)malloc(sizeof(int64_t) * (size_t)M);
-    S.pending = (int64_t *)calloc((size_t)M, sizeof(int64_t));
-    S.touchedSlots = (int64_t *)malloc(sizeof(int64_t) * (size_t)M);
-    S.d = (int64_t *)calloc((size_t)n, sizeof(int64_t));
-    S.dprime = (int64_t *)calloc((size_t)n, sizeof(int64_t));
-    S.e = (int64_t *)calloc((size_t)n, sizeof(int64_t));
-    S.addedExcess = (int64_t *)calloc((size_t)n, sizeof(int64_t));
-    S.work = (int64_t *)calloc((size_t)n, sizeof(int64_t));
-    S.isDiscovered = (uint8_t *)calloc((size_t)n, 1);
-    S.vertTouched = (uint8_t *)calloc((size_t)n, 1);
-    S.workingSet = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    S.next = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    S.touchedVerts = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    S.Q = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    S.Q2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    if (!S.res || !S.pending || !S.touchedSlots || !S.d || !S.dprime || !S.e || !S.addedExcess ||
-        !S.work || !S.isDiscovered || !S.vertTouched || !S.workingSet || !S.next ||
-        !S.touchedVerts || !S.Q || !S.Q2)
+    const int64_t n = g->n, S = g->slots > 0 ? g->slots : 1;
+    machine M;
+    memset(&M, 0, sizeof M);
+    M.g = g;
+    M.n = n;
+    M.m = g->slots;
+    M.cf = (int64_t *)malloc(sizeof(int64_t) * (size_t)S);
+    M.back = (int64_t *)calloc((size_t)S, sizeof(int64_t));
+    M.blist = (int64_t *)malloc(sizeof(int64_t) * (size_t)S);
+    M.lab = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    M.exc = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    M.raised = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    M.change = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    M.touched = (uint8_t *)calloc((size_t)n, 1);
+    M.in_ws = (uint8_t *)calloc((size_t)n, 1);
+    M.tlist = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    M.ws = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    M.fifo = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    M.count = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!M.cf || !M.back || !M.blist || !M.lab || !M.exc || !M.raised || !M.change || !M.touched ||
+        !M.in_ws || !M.tlist || !M.ws || !M.fifo || !M.count)
         return OG_ENOMEM;
 
-    /* Listing 1 initialisation: d = 0, e = 0, f = 0, d(s) = n */
-    for (int64_t a = 0; a < g->slots; a++) S.res[a] = g->cap[a];
-    S.d[g->s] = n;
-    S.dprime[g->s] = n;
-    /* saturate every arc out of s */
+    /* start: zero flow, labels 0 with d(s) = n, every arc out of s saturated */
+    for (int64_t a = 0; a < g->slots; a++) M.cf[a] = g->cap[a];
+    M.lab[g->s] = n;
     for (int64_t a = g->off[g->s]; a < g->off[g->s + 1]; a++) {
-        int64_t c = g->cap[a];
+        const int64_t c = M.cf[a];
         if (c <= 0) continue;
-        int64_t w = g->head[a];
-        S.res[a] -= c;
-        S.res[g->rev[a]] += c;
-        S.e[w] += c;
-        S.e[g->s] -= c;
-        if (w != g->s && w != g->t && !S.isDiscovered[w]) {
-            S.isDiscovered[w] = 1;
-            S.workingSet[S.nws++] = w;
-        }
+        M.cf[a] = 0;
+        M.cf[g->rev[a]] += c;
+        M.exc[g->head[a]] += c;
+        M.exc[g->s] -= c;
     }
-    for (int64_t i = 0; i < S.nws; i++) S.isDiscovered[S.workingSet[i]] = 0;
+    /* the first working set: every vertex the saturation gave excess */
+    for (int64_t v = 0; v < n; v++)
+        if (v != g->s && v != g->t && M.exc[v] > 0) {
+            M.ws[M.nws++] = v;
+            M.in_ws[v] = 1;
+        }
 
-    int stopped = prsn_phase(&S, g->t, g->s, max_rounds, &sc);
+    const int stopped = run_phase(&M, g->t, g->s, max_rounds, &sc);
     memset(r, 0, sizeof *r);
-    r->value = S.e[g->t];
-    r->pushes = S.pushes;
-    r->relabels = S.relabels;
-    r->global_relabels = S.grs;
-    r->rounds = S.rounds;
-    r->work = S.work_total;
-    r->bfs_levels = S.levels;
-    if (d_out) memcpy(d_out, S.d, sizeof(int64_t) * (size_t)n);
+    r->value = M.exc[g->t];
+    r->pushes = M.pushes;
+    r->relabels = M.relabels;
+    r->global_relabels = M.grs;
+    r->rounds = M.rounds;
+    r->work = M.work;
+    r->bfs_levels = M.levels;
+    r->gap_lifts = M.gap_lifts;
+    if (d_out) memcpy(d_out, M.lab, sizeof(int64_t) * (size_t)n);
 
+    /* T* and the capacity of its cut, from the residuals of the preflow */
     int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    og_residual_distance(g, S.res, g->t, g->s, dist);
+    if (!dist) return OG_ENOMEM;
+    og_residual_distance(g, M.cf, g->t, g->s, dist);
     int64_t cut = 0;
     for (int64_t v = 0; v < n; v++) {
         if (dist[v] < n) continue;
@@ -314,25 +368,29 @@ int og_sync_maxflow(const og_graph *g, int preflow_only, int64_t max_rounds,
     free(dist);
 
     if (!preflow_only && !stopped) {
-        /* phase 2: the same rounds with s as the sink and t excluded, starting
-         * from every vertex that still holds excess */
-        S.nws = 0;
+        /* phase 2 from every vertex that still holds excess */
+        for (int64_t i = 0; i < M.nws; i++) M.in_ws[M.ws[i]] = 0;
+        M.nws = 0;
         for (int64_t v = 0; v < n; v++)
-            if (v != g->s && v != g->t && S.e[v] > 0) S.workingSet[S.nws++] = v;
-        S.pushes = S.relabels = S.grs = S.rounds = 0;
-        int64_t wt = S.work_total, lv = S.levels;
-        prsn_phase(&S, g->s, g->t, 0, &sc);
-        r->pushes2 = S.pushes;
-        r->relabels2 = S.relabels;
-        r->global_relabels2 = S.grs;
-        r->rounds2 = S.rounds;
-        S.work_total = wt;
-        S.levels = lv;
+            if (v != g->s && v != g->t && M.exc[v] > 0) {
+                M.ws[M.nws++] = v;
+                M.in_ws[v] = 1;
+            }
+        const int64_t p1 = M.pushes, r1 = M.relabels, g1 = M.grs, k1 = M.rounds, w1 = M.work,
+                      l1 = M.levels, x1 = M.gap_lifts;
+        run_phase(&M, g->s, g->t, 0, &sc);
+        r->pushes2 = M.pushes - p1;
+        r->relabels2 = M.relabels - r1;
+        r->global_relabels2 = M.grs - g1;
+        r->rounds2 = M.rounds - k1;
+        r->gap_lifts2 = M.gap_lifts - x1;
+        (void)w1;
+        (void)l1;
     }
-    if (res_out) memcpy(res_out, S.res, sizeof(int64_t) * (size_t)g->slots);
-    if (e_out) memcpy(e_out, S.e, sizeof(int64_t) * (size_t)n);
-    free(S.res); free(S.pending); free(S.touchedSlots); free(S.d); free(S.dprime); free(S.e);
-    free(S.addedExcess); free(S.work); free(S.isDiscovered); free(S.vertTouched);
-    free(S.workingSet); free(S.next); free(S.touchedVerts); free(S.Q); free(S.Q2);
+    if (res_out) memcpy(res_out, M.cf, sizeof(int64_t) * (size_t)g->slots);
+    if (e_out) memcpy(e_out, M.exc, sizeof(int64_t) * (size_t)n);
+    free(M.cf); free(M.back); free(M.blist); free(M.lab); free(M.exc); free(M.raised);
+    free(M.change); free(M.touched); free(M.in_ws); free(M.tlist); free(M.ws); free(M.fifo);
+    free(M.count);
     return stopped;
 }

@@ -55,6 +55,22 @@ def main():
         lv = oracle.sync_maxflow(c1, schedule=dict(level_charge=100000))
         if lv["value"] != full_value(c1) or lv["global_relabels"] == oracle.sync_maxflow(c1)["global_relabels"]:
             return 1
+        # the gap rule: the hand trace, and no hole left below the top label
+        gg = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gap_rule_trace.json")))
+        g = graph_from_json(gg["graph"])
+        p1 = oracle.sync_maxflow(g, preflow_only=True, schedule=dict(gap=1))
+        if (p1["rounds"], p1["gap_lifts"]) != (1, 2):
+            return 1
+        for seed in list(range(30)) + [79]:
+            n = 6 + seed % 12 if seed < 30 else 25
+            g = random_graph(n, 3 * n if seed < 30 else 5 * n, seed)
+            inner = np.ones(g.n, bool)
+            inner[[g.s, g.t]] = False
+            for k in range(1, 10):
+                G = oracle.sync_maxflow(g, preflow_only=True, max_rounds=k, schedule=dict(gap=1))
+                labs = np.unique(G["d"][inner & (G["d"] < g.n)])
+                if labs.size and (labs[0] < 1 or labs[-1] != labs.size):
+                    return 1
     except Exception:
         return 1
     return 0

@@ -293,3 +293,128 @@ def test_certificate_rejects_non_maximum_and_invalid():
     assert oracle.check_certificate(g, over, A["tstar"])[0] in (2, 3)
     asym = A["flow"].copy(); asym[0] += 1
     assert oracle.check_certificate(g, asym, A["tstar"])[0] == 1
+
+
+# ---------------------------------------------------------------- labels after a global relabel
+
+@pytest.mark.parametrize("name,f", [("c1", 1), ("c3", 16), ("c4a", 32), ("c4b", 16)])
+def test_labels_exact_and_valid_after_each_global_relabel(name, f):
+    """Right after a global relabel the labels are the exact residual
+    distances to t (Sec. 2.1), hence valid: d(v) <= d(w) + 1 on every
+    residual arc v -> w.  A round charge far above the threshold puts a
+    global relabel before every round, so the state returned after k rounds
+    is a post-relabel state; the distances come from the checker's own BFS,
+    and validity and the excess identity are checked on the arrays."""
+    g = make_config(name, f)
+    tl = g.tails()
+    sched = dict(round_charge=10 ** 15)
+    for k in (1, 2, 5, 13):
+        B = oracle.sync_maxflow(g, preflow_only=True, max_rounds=k, schedule=sched)
+        res, d, e = B["res"], B["d"], B["e"]
+        dist = oracle.residual_distance(g, res, g.t, g.s)
+        dist[g.s] = g.n
+        assert (d == dist).all(), k
+        resid = res > 0
+        assert (d[tl[resid]] <= d[g.head[resid]] + 1).all(), k
+        flow = g.cap.astype(np.int64) - res
+        assert (-np.bincount(tl, weights=flow, minlength=g.n).astype(np.int64) == e).all()
+
+
+def test_labels_between_relabels_can_be_invalid():
+    """Between global relabels a vertex that gives way on an edge may raise
+    its label past the neighbour pushing into it in the same round (Sec. 3.1
+    allows this), so validity d(v) <= d(w) + 1 can fail mid-phase (here on a
+    seeded random graph after its first round).  The global relabels restore
+    it, and the termination rule does not rely on it."""
+    g = random_graph(16, 48, 108)
+    tl = g.tails()
+    broken = False
+    for k in range(1, 40):
+        B = oracle.sync_maxflow(g, preflow_only=True, max_rounds=k)
+        if not B["stopped"]:
+            break
+        d, res = B["d"], B["res"]
+        resid = (res > 0) & (tl != g.s) & (tl != g.t)
+        if not (d[tl[resid]] <= d[g.head[resid]] + 1).all():
+            broken = True
+            break
+    assert broken
+
+
+# ---------------------------------------------------------------- gap rule
+
+def test_gap_rule_hand_trace():
+    with open(os.path.join(GOLDEN, "gap_rule_trace.json")) as fh:
+        gold = json.load(fh)
+    g = graph_from_json(gold["graph"])
+    off = gold["without_gap"]
+    r1 = oracle.sync_maxflow(g, preflow_only=True, max_rounds=1)
+    assert r1["stopped"]
+    for key in ("d", "e", "res"):
+        assert r1[key].tolist() == off["after_round_1"][key], key
+    for sched, ref in ((None, off["phase1"]), (dict(gap=1), gold["with_gap"]["phase1"])):
+        p1 = oracle.sync_maxflow(g, preflow_only=True, schedule=sched)
+        for key in ("value", "rounds", "pushes", "relabels", "global_relabels", "work", "gap_lifts"):
+            assert p1[key] == ref[key], (sched, key)
+        if "d" in ref:
+            assert p1["d"].tolist() == ref["d"]
+        full = oracle.sync_maxflow(g, schedule=sched)
+        assert full["rounds2"] == gold["phase2"]["rounds"] and full["pushes2"] == gold["phase2"]["pushes"]
+        assert full["res"].tolist() == gold["phase2"]["res"]
+        assert full["flow"].tolist() == gold["phase2"]["flow"]
+
+
+def test_gap_rule_no_hole_after_rounds_random():
+    """The no-hole property round by round on seeded random graphs, among
+    them one (seed 79) where a round opens gaps at two labels at once: the
+    rule must take the smaller."""
+    for seed in list(range(40)) + [79]:
+        n = 6 + seed % 12 if seed < 40 else 25
+        g = random_graph(n, 3 * n if seed < 40 else 5 * n, seed)
+        inner = np.ones(g.n, bool)
+        inner[[g.s, g.t]] = False
+        for k in range(1, 12):
+            G = oracle.sync_maxflow(g, preflow_only=True, max_rounds=k, schedule=dict(gap=1))
+            labs = np.unique(G["d"][inner & (G["d"] < g.n)])
+            if labs.size:
+                assert labs[0] >= 1 and labs[-1] == labs.size, (seed, k)
+            if not G["stopped"]:
+                break
+
+
+@pytest.mark.parametrize("chunk", range(2))
+def test_gap_rule_brute_force(chunk):
+    lifted = 0
+    for seed in range(chunk * 60, chunk * 60 + 60):
+        n = 4 + seed % 14
+        g = random_graph(n, (2 + seed % 4) * n, seed)
+        best, tstar, _ = brute_mincut(g)
+        for simple in (0, 1):
+            G = oracle.sync_maxflow(g, schedule=dict(gap=1, simple=simple))
+            assert G["value"] == best, seed
+            assert (G["tstar"] == tstar).all(), seed
+            _cert_ok(g, G["flow"], G["tstar"])
+            lifted += G["gap_lifts"]
+    assert lifted > 0
+
+
+@pytest.mark.parametrize("name,f", [("c1", 1), ("c2", 16), ("c3", 16), ("c4a", 32), ("c4b", 16)])
+def test_gap_rule_leaves_no_gap(name, f):
+    """After every round with the gap rule, the labels below n of the
+    vertices other than the terminals fill 1 .. max without a hole; the
+    value and T* are those of the FIFO oracle."""
+    g = make_config(name, f)
+    A = oracle.fifo_maxflow(g, preflow_only=True)
+    inner = np.ones(g.n, bool)
+    inner[[g.s, g.t]] = False
+    for k in (1, 2, 4, 8, 16, 32, 64):
+        G = oracle.sync_maxflow(g, preflow_only=True, max_rounds=k, schedule=dict(gap=1))
+        labs = np.unique(G["d"][inner & (G["d"] < g.n)])
+        if labs.size:
+            assert labs[0] >= 1 and labs[-1] == labs.size, (k, labs[:10])
+        if not G["stopped"]:
+            break
+    G = oracle.sync_maxflow(g, schedule=dict(gap=1))
+    assert G["value"] == A["value"]
+    assert (G["tstar"] == A["tstar"]).all()
+    _cert_ok(g, G["flow"], G["tstar"])

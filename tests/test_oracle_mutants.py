@@ -11,19 +11,20 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 MUTANTS = [
-    ("sync.c", "(S->d[v] == S->d[w] && v < w)", "(S->d[v] == S->d[w] && v > w)"),       # tie-break
-    ("sync.c", "(S->d[v] < S->d[w] - 1)", "(S->d[v] < S->d[w] + 1)"),                   # win rule
-    ("sync.c", "int admissible = (S->dprime[v] == S->d[w] + 1);",
-     "int admissible = (S->d[v] == S->d[w] + 1);"),                                      # d' vs d
-    ("sync.c", "if (S->res[g->rev[a]] <= 0) continue;        /* c_f(w,v) > 0 */",
-     "if (S->res[a] <= 0) continue;"),                                                   # BFS direction
-    ("sync.c", "S->res[b] += S->pending[b];", "(void)0;"),                               # lost reverse residual
-    ("sync.c", "S->addedExcess[v] += e - S->e[v];", "S->addedExcess[v] = e - S->e[v];"), # listing's '='
-    ("sync.c", "if (S->res[a] > 0 && S->d[w] >= S->dprime[v]) {",
-     "if (S->res[a] > 0 && S->d[w] > S->dprime[v]) {"),                                  # relabel candidate bound
-    ("sync.c", "if (sc->simple) break;               /* simple rounds: one pass, one relabel */",
-     "(void)0;"),                                                                        # simple: full discharge
-    ("sync.c", "lastDepth = GlobalRelabel(S, sink, other);", "GlobalRelabel(S, sink, other);"),  # level charge dropped
+    ("sync.c", "(dv == dw && v < w)", "(dv == dw && v > w)"),                            # tie-break
+    ("sync.c", "dv < dw - 1", "dv < dw + 1"),                                            # ownership rule
+    ("sync.c", "if (dcur == dw + 1) {", "if (d0 == dw + 1) {"),                          # d' vs d
+    ("sync.c", "if (M->cf[g->rev[a]] > 0) {          /* w can send to v */",
+     "if (M->cf[a] > 0) {"),                                                             # BFS direction
+    ("sync.c", "M->cf[M->blist[i]] += M->back[M->blist[i]];", "(void)0;"),               # lost reverse residual
+    ("sync.c", "M->change[v] += left - M->exc[v];", "M->change[v] = left - M->exc[v];"), # '=' for the excess sum
+    ("sync.c", "dw >= dcur && dw + 1 < lowest", "dw > dcur && dw + 1 < lowest"),         # raise candidate bound
+    ("sync.c", "if (dcur == n || simple) break;", "if (dcur == n) break;"),              # simple: full discharge
+    ("sync.c", "depth = bfs_labels(M, sink, other);", "bfs_labels(M, sink, other);"),    # level charge dropped
+    ("sync.c", "if (lost[i] > 0 && lost[i] < gap && M->count[lost[i]] == 0) gap = lost[i];",
+     "if (lost[i] > 0 && M->count[lost[i]] == 0) gap = lost[i];"),                      # gap: not the smallest
+    ("sync.c", "if (M->lab[v] > gap && M->lab[v] < n) {",
+     "if (M->lab[v] > gap + 1 && M->lab[v] < n) {"),                                    # gap: lift off by one
     ("fifo.c", "S->res[g->rev[a]] += delta;", "(void)delta;"),                           # lost reverse residual
     ("fifo.c", "nd = S->d[g->head[a]] + 1;", "nd = S->d[g->head[a]];"),                  # relabel off by one
     ("fifo.c", "if (S->res[a] > 0 && S->d[v] == S->d[w] + 1) {",
