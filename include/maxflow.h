@@ -62,8 +62,13 @@ typedef enum {
     MF_ETIMEOUT = 4,   /* max_rounds reached; outputs hold a valid preflow */
     MF_EAGAIN = 5,     /* not finished yet (server poll) or no free slot */
     MF_ECANCELED = 6,  /* request canceled */
-    MF_ENOTFOUND = 7   /* unknown ticket or handle */
+    MF_ENOTFOUND = 7,  /* unknown ticket or handle */
+    MF_EINVARIANT = 8  /* MF_CHECK_INVARIANTS found a broken invariant (see mf_last_error) */
 } mf_status;
+
+/* A HIP stream (the type hipStream_t names), declared here so that the header
+ * needs no HIP include.  NULL is the null stream. */
+typedef struct ihipStream_t *mf_stream;
 
 typedef struct {
     int32_t n;
@@ -104,6 +109,19 @@ typedef struct {
                                   sink side are those of the new graph.  MF_EINVAL if the context
                                   holds no resumable state for the graph.  Uses the grid-wide
                                   kernels whatever the graph's size */
+#define MF_CHECK_INVARIANTS 0x40u  /* debug mode: after every round and every global relabel the
+                                  solve checks the state on the device and stops with
+                                  MF_EINVARIANT at the first violation: residuals >= 0 and
+                                  res[a] + res[rev a] = cap[a] + cap[rev a] (the flow stays
+                                  within capacity and antisymmetric, Eq. 1-2); no push left
+                                  pending between rounds; every excess equals the net inflow
+                                  the residuals give and is >= 0 off s (a preflow, Sec. 2.1);
+                                  labels in [0, n] with d(sink) = 0 and d(excluded
+                                  terminal) = n; after a global relabel also
+                                  d(v) <= d(w) + 1 on every residual arc v -> w (exact
+                                  distances are valid labels, Sec. 2.1).  Rounds run one per
+                                  read-back in this mode, and the grid-wide kernels solve
+                                  every graph */
 #define MF_SMALL_N      8192
 #define MF_SMALL_SLOTS  16384
 
@@ -136,7 +154,9 @@ typedef struct {
     int32_t profile_stride;      /* with MF_PROFILE: time every profile_stride-th launch of each
                                     timed kernel (0 or 1 = every launch), which bounds the device
                                     time the events cost; counts and bytes cover every launch */
-    int32_t reserved[1];
+    int32_t check_fault_round;   /* test hook for MF_CHECK_INVARIANTS (0 = off): after this many
+                                    rounds of phase 1 the host raises one residual by 1 before the
+                                    check runs, which must then stop the solve with MF_EINVARIANT */
 } mf_options;
 
 typedef struct {
@@ -216,14 +236,25 @@ const char *mf_last_error(const mf_context *ctx);
 mf_status mf_context_create(int device, size_t hbm_budget_bytes, mf_context **out);
 void mf_context_destroy(mf_context *ctx);
 
-/* Step 1 of a solve (residency and validation): copies the graph into
+/* Stream ordering of the calls below that take a `stream`: the library's
+ * work on the caller's device buffers is ordered after all work enqueued on
+ * `stream` before the call (so a kernel that is still writing an input on
+ * that stream finishes first; no device-wide synchronize is needed), and
+ * work enqueued on `stream` after the call returns is ordered after the
+ * library's writes to the outputs.  The calls return when their outputs are
+ * complete.  `stream` must not be capturing a graph. */
+
+/* Step 1 of a solve (residency and validation; the graph model of Sec. 2 in
+ * the adjacency representation of Sec. 4.2): copies the graph into
  * library-owned device memory, narrows offsets and rev to int32 and checks
  * it (rev is an involution with matching heads, heads in range, no
  * self-loops, cap >= 0, pair sums below 2^31, s != t).  `g` holds host
  * pointers when on_device = 0 and device pointers when on_device = 1 (then
- * they must stay valid until this call returns).  Returns MF_EINVAL for an
- * invalid graph, MF_ENOMEM beyond the budget. */
-mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_dgraph **out);
+ * they must stay valid until this call returns; they are read in the order
+ * of `stream`).  Returns MF_EINVAL for an invalid graph, MF_ENOMEM beyond the
+ * budget. */
+mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_stream stream,
+                          mf_dgraph **out);
 void mf_graph_free(mf_context *ctx, mf_dgraph *dg);
 
 /* Replaces the capacities of an uploaded graph (the structure stays):
@@ -239,24 +270,34 @@ void mf_graph_free(mf_context *ctx, mf_dgraph *dg);
  * can continue from that flow; otherwise 0, and the next solve starts from
  * zero flow. */
 mf_status mf_graph_set_caps(mf_context *ctx, mf_dgraph *dg, const int32_t *cap, int on_device,
-                            int *resumable);
+                            mf_stream stream, int *resumable);
 
-/* Solves an uploaded graph on the context's stream.  flow_dev (int32[slots])
- * and side_dev (uint8[n]) are device pointers that receive the outputs, or
- * NULL to skip them; flow_dev must be NULL with MF_PREFLOW_ONLY.  The call
- * returns when the outputs are complete.  value / stats may be NULL. */
-mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt,
+/* Solves an uploaded graph: a maximum flow and a minimum cut (Sec. 2,
+ * Eq. 1-2, max-flow min-cut).  Phase 1 is the synchronous push-relabel of
+ * Sec. 3.1 with global relabels (Sec. 2.1, Sec. 3) up to a maximum preflow,
+ * whose value is the flow value and whose residual graph gives the sink side
+ * T* (Sec. 2.1); phase 2 turns the preflow into a flow by returning the
+ * excess that cannot reach t to s (Sec. 2.1 second phase).  flow_dev
+ * (int32[slots]) and side_dev (uint8[n]) are device pointers that receive the
+ * outputs, or NULL to skip them; flow_dev must be NULL with MF_PREFLOW_ONLY.
+ * The kernels run on the context's stream, ordered against `stream` as
+ * stated above.  value / stats may be NULL.  MF_ETIMEOUT: max_rounds reached
+ * (the outputs then describe a valid preflow); MF_EINVARIANT: see
+ * MF_CHECK_INVARIANTS. */
+mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, mf_stream stream, const mf_options *opt,
                             int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
                             mf_stats *stats);
 
-/* Upload + solve + copy-out for host buffers: flow (int32[slots]) and
+/* The solve of mf_solve_uploaded (same method, Sec. 2, 2.1, 3.1) for a graph
+ * in host memory: upload + solve + copy-out; flow (int32[slots]) and
  * sink_side (uint8[n]) are host pointers or NULL. */
 mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_options *opt,
                    int64_t *value, int32_t *flow, uint8_t *sink_side, mf_stats *stats);
 
-/* The same for a graph and outputs already in device memory (for example
- * torch tensors); the call returns when the outputs are complete. */
-mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, const mf_options *opt,
+/* The solve of mf_solve_uploaded (same method, Sec. 2, 2.1, 3.1) for a graph
+ * and outputs already in device memory (for example torch tensors), read and
+ * written in the order of `stream` (see above). */
+mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, mf_stream stream, const mf_options *opt,
                           int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
                           mf_stats *stats);
 
@@ -281,7 +322,8 @@ typedef struct {
     double ms_latency;           /* server: time from mf_server_submit to the result being ready */
 } mf_result;
 
-/* Solves k graphs given in host memory.  opts is NULL (the defaults for all)
+/* Solves k graphs given in host memory, each by the method of
+ * mf_solve_uploaded (Sec. 2, 2.1, 3.1).  opts is NULL (the defaults for all)
  * or an array of k options (per-instance schedules, e.g. from the autotuner;
  * lanes_per_vertex 0 = automatic, otherwise 4, 8, 16 or 32).  flows[i] /
  * sides[i] are host buffers (int32[slots_i] / uint8[n_i]) or NULL, and flows

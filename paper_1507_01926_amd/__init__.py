@@ -16,15 +16,17 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmaxflow.so")
 
-MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ETIMEOUT, MF_EAGAIN, MF_ECANCELED, MF_ENOTFOUND = range(8)
+MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ETIMEOUT, MF_EAGAIN, MF_ECANCELED, MF_ENOTFOUND, \
+    MF_EINVARIANT = range(9)
 STATUS_NAMES = {0: "MF_OK", 1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ETIMEOUT",
-                5: "MF_EAGAIN", 6: "MF_ECANCELED", 7: "MF_ENOTFOUND"}
+                5: "MF_EAGAIN", 6: "MF_ECANCELED", 7: "MF_ENOTFOUND", 8: "MF_EINVARIANT"}
 MF_PREFLOW_ONLY = 0x1
 MF_PROFILE = 0x2
 MF_PERSISTENT = 0x4
 MF_GRID_PATH = 0x8
 MF_SIMPLE_ROUNDS = 0x10
 MF_WARM_START = 0x20
+MF_CHECK_INVARIANTS = 0x40
 
 
 class MaxflowError(RuntimeError):
@@ -49,7 +51,7 @@ class mf_options(ctypes.Structure):
                 ("lanes_per_merge", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_bfs", ctypes.c_int32),
                 ("profile_mask", ctypes.c_uint32), ("bfs_bottom_up_factor", ctypes.c_int32),
-                ("profile_stride", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("profile_stride", ctypes.c_int32), ("check_fault_round", ctypes.c_int32)]
 
 
 class mf_stats(ctypes.Structure):
@@ -101,12 +103,12 @@ SIGNATURES = [
     ("mf_last_error", ctypes.c_char_p, [_P]),
     ("mf_context_create", ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, _P]),
     ("mf_context_destroy", None, [_P]),
-    ("mf_graph_upload", ctypes.c_int, [_P, _P, ctypes.c_int, _P]),
+    ("mf_graph_upload", ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
     ("mf_graph_free", None, [_P, _P]),
-    ("mf_graph_set_caps", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
-    ("mf_solve_uploaded", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("mf_graph_set_caps", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P]),
+    ("mf_solve_uploaded", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
-    ("mf_solve_device", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("mf_solve_device", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     ("mf_batch_solve", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
     ("mf_server_create", ctypes.c_int, [_P, _P, _P]),
     ("mf_server_destroy", None, [_P]),
@@ -162,9 +164,25 @@ def options(**kw) -> mf_options:
             o.flags = (o.flags | MF_SIMPLE_ROUNDS) if v else (o.flags & ~MF_SIMPLE_ROUNDS)
         elif k == "warm_start":
             o.flags = (o.flags | MF_WARM_START) if v else (o.flags & ~MF_WARM_START)
+        elif k == "check_invariants":
+            o.flags = (o.flags | MF_CHECK_INVARIANTS) if v else (o.flags & ~MF_CHECK_INVARIANTS)
         else:
             setattr(o, k, int(v))
     return o
+
+
+def _stream(stream):
+    """The HIP stream handle to order a call against: an explicit handle (int
+    or torch stream), else torch's current stream, else the null stream."""
+    if stream is None:
+        try:
+            import torch
+            return int(torch.cuda.current_stream().cuda_stream) or None
+        except Exception:
+            return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream) or None
+    return int(stream) or None
 
 
 def _stats_dict(s: mf_stats) -> dict:
@@ -238,34 +256,37 @@ class Context:
     def upload(self, g) -> "DeviceGraph":
         hg = _HostGraph(g)
         h = ctypes.c_void_p()
-        self._check(lib().mf_graph_upload(self.h, ctypes.byref(hg.st), 0, ctypes.byref(h)))
+        self._check(lib().mf_graph_upload(self.h, ctypes.byref(hg.st), 0, None, ctypes.byref(h)))
         return DeviceGraph(self, h, g.n, hg.head.shape[0])
 
-    def upload_device(self, off, head, rev, cap, s, t) -> "DeviceGraph":
-        """Graph arrays given as device pointers (e.g. torch tensors on cuda)."""
+    def upload_device(self, off, head, rev, cap, s, t, stream=None) -> "DeviceGraph":
+        """Graph arrays given as device pointers (e.g. torch tensors on cuda),
+        read in the order of `stream` (default: torch's current stream)."""
         n = int(off.numel()) - 1
         S = int(head.numel())
         gst = mf_graph(n, S, off.data_ptr(), head.data_ptr(), rev.data_ptr(), cap.data_ptr(),
                        int(s), int(t))
         h = ctypes.c_void_p()
-        self._check(lib().mf_graph_upload(self.h, ctypes.byref(gst), 1, ctypes.byref(h)))
+        self._check(lib().mf_graph_upload(self.h, ctypes.byref(gst), 1, _stream(stream), ctypes.byref(h)))
         return DeviceGraph(self, h, n, S)
 
     def solve_device(self, off, head, rev, cap, s, t, flow=None, side=None,
-                     opt: mf_options | None = None) -> dict:
-        """mf_solve_device: inputs and outputs are device buffers (torch tensors)."""
+                     opt: mf_options | None = None, stream=None, allow_status=()) -> dict:
+        """mf_solve_device: inputs and outputs are device buffers (torch tensors),
+        ordered against `stream` (default: torch's current stream)."""
         n = int(off.numel()) - 1
         S = int(head.numel())
         gst = mf_graph(n, S, off.data_ptr(), head.data_ptr(), rev.data_ptr(), cap.data_ptr(),
                        int(s), int(t))
         val = ctypes.c_int64(0)
         stats = mf_stats()
-        st = lib().mf_solve_device(self.h, ctypes.byref(gst), ctypes.byref(opt or options()),
+        st = lib().mf_solve_device(self.h, ctypes.byref(gst), _stream(stream), ctypes.byref(opt or options()),
                                    ctypes.byref(val), None if flow is None else flow.data_ptr(),
                                    None if side is None else side.data_ptr(), ctypes.byref(stats))
-        self._check(st)
+        if st not in allow_status:
+            self._check(st)
         out = _stats_dict(stats)
-        out.update(value=int(val.value))
+        out.update(status=st, value=int(val.value))
         return out
 
 
@@ -324,17 +345,18 @@ class DeviceGraph:
         if c.shape[0] != self.slots:
             raise ValueError("cap must have one entry per slot")
         res = ctypes.c_int(0)
-        self.ctx._check(lib().mf_graph_set_caps(self.ctx.h, self.h, c.ctypes.data, 0, ctypes.byref(res)))
+        self.ctx._check(lib().mf_graph_set_caps(self.ctx.h, self.h, c.ctypes.data, 0, None, ctypes.byref(res)))
         return bool(res.value)
 
     def solve(self, opt: mf_options | None = None, flow_ptr=None, side_ptr=None,
-              allow_timeout=False) -> dict:
-        """mf_solve_uploaded; flow_ptr / side_ptr are device addresses or None."""
+              allow_timeout=False, stream=None, allow_status=()) -> dict:
+        """mf_solve_uploaded; flow_ptr / side_ptr are device addresses or None,
+        written in the order of `stream` (default: torch's current stream)."""
         val = ctypes.c_int64(0)
         stats = mf_stats()
-        st = lib().mf_solve_uploaded(self.ctx.h, self.h, ctypes.byref(opt or options()),
+        st = lib().mf_solve_uploaded(self.ctx.h, self.h, _stream(stream), ctypes.byref(opt or options()),
                                      ctypes.byref(val), flow_ptr, side_ptr, ctypes.byref(stats))
-        if not (allow_timeout and st == MF_ETIMEOUT):
+        if not (allow_timeout and st == MF_ETIMEOUT) and st not in allow_status:
             self.ctx._check(st)
         out = _stats_dict(stats)
         out.update(status=st, value=int(val.value))

@@ -184,6 +184,51 @@ __global__ void k_saturate(GraphView g, StateView st)
 }
 
 // ---------------------------------------------------------------------------
+// State checks between rounds (MF_CHECK_INVARIANTS).  One thread per vertex
+// walks the vertex's slots; bits of ctl->inv_err:
+//   1  a residual below 0 (a flow above its capacity, Eq. 1)
+//   2  res[a] + res[rev a] != cap[a] + cap[rev a] (antisymmetry, Eq. 1)
+//   4  a push still pending (delta != 0) at a round boundary
+//   8  an excess other than that of s differs from the net inflow its
+//      residuals give (s's excess is not tracked: it is never read)
+//   16 an excess below 0 at a vertex other than s (not a preflow)
+//   32 a label outside [0, n], d(sink) != 0 or d(excluded terminal) != n
+//   64 after a global relabel: d(v) > d(w) + 1 on a residual arc v -> w
+//      (exact distances are valid labels, Sec. 2.1)
+//   128 a touched mark left set between rounds
+__global__ void k_check_state(GraphView g, StateView st, int sink, int other, int after_gr, Ctl *ctl)
+{
+    int err = 0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+        const int beg = g.off[v], end = g.off[v + 1];
+        const int dv = st.d[v];
+        if (dv < 0 || dv > g.n || (v == sink && dv != 0) || (v == other && dv != g.n)) err |= 32;
+        if (st.touched[v]) err |= 128;
+        int64_t net = 0;
+        for (int a = beg; a < end; a++) {
+            const int r = st.res[a], b = g.rev[a];
+            if (r < 0) err |= 1;
+            if ((int64_t)r + st.res[b] != (int64_t)g.cap[a] + g.cap[b]) err |= 2;
+            if (st.delta[a] != 0) err |= 4;
+            net += (int64_t)r - g.cap[a];
+            if (after_gr && r > 0 && v != other) {
+                const int w = g.head[a];
+                if (w != other && dv > st.d[w] + 1) err |= 64;
+            }
+        }
+        if (v != g.s) {
+            if (st.e[v] != net) err |= 8;
+            if (st.e[v] < 0) err |= 16;
+        }
+    }
+    if (err) atomicOr(&ctl->inv_err, err);
+}
+
+// Test hook of MF_CHECK_INVARIANTS: raises one residual by 1.
+__global__ void k_bump(int32_t *p) { *p += 1; }
+
+// ---------------------------------------------------------------------------
 // Global relabel (Listing 2): d(v) = n for all v, d(sink) = 0, then one
 // breadth-first level at a time.  w gets label L+1 when it has a residual arc
 // w -> v into a vertex v of label L (c_f(w,v) > 0: the residual capacity of
@@ -875,6 +920,13 @@ void launch_flow(GraphView g, const int32_t *res, int32_t *flow, int grid, hipSt
 {
     hipLaunchKernelGGL(k_flow, dim3(grid), dim3(256), 0, s, g, res, flow);
 }
+void launch_check_state(GraphView g, StateView st, int sink, int other, int after_gr, int grid, hipStream_t s)
+{
+    k_check_state<<<grid, 256, 0, s>>>(g, st, sink, other, after_gr, st.ctl);
+}
+
+void launch_bump(int32_t *p, hipStream_t s) { k_bump<<<1, 1, 0, s>>>(p); }
+
 void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s)
 {
     hipLaunchKernelGGL(k_read_value, dim3(1), dim3(1), 0, s, e, t, ctl);

@@ -52,6 +52,7 @@ struct Ctl {
     int64_t fdeg[3];
     int64_t gr_found_deg;
     int64_t td_slots;      // profiling: slots expanded by the top-down levels of a relabel
+    int32_t inv_err;       // MF_CHECK_INVARIANTS: bits of the checks that failed (k_check_state)
 };
 
 // Parameters of a discharge step (host-built, passed to the kernels by value).

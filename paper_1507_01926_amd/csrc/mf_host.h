@@ -60,6 +60,7 @@ struct mf_context {
     hipEvent_t pev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // profiling
     hipStream_t bstream[4] = {nullptr, nullptr, nullptr, nullptr};                 // batch groups
     hipEvent_t bev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t sev[2] = {nullptr, nullptr};   // ordering against a caller's stream (in, out)
     std::vector<hipEvent_t> lev;     // profiling of batched levels, created on first use
     Workspace ws;
     uint8_t *one = nullptr;    // device: item, result, queue and order of a single-workgroup solve

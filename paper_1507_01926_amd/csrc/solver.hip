@@ -67,6 +67,8 @@ void launch_side(GraphView g, const int32_t *d, uint8_t *side, int grid, hipStre
 void launch_cut(GraphView g, const uint8_t *side, Ctl *ctl, int grid, hipStream_t s);
 void launch_flow(GraphView g, const int32_t *res, int32_t *flow, int grid, hipStream_t s);
 void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s);
+void launch_check_state(GraphView g, StateView st, int sink, int other, int after_gr, int grid, hipStream_t s);
+void launch_bump(int32_t *p, hipStream_t s);
 
 
 }  // namespace mf
@@ -74,6 +76,7 @@ void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s);
 using namespace mf;
 
 thread_local std::string g_global_err;
+
 
 // ---------------------------------------------------------------------------
 // Public helpers
@@ -113,6 +116,7 @@ const char *mf_status_str(mf_status s)
     case MF_EAGAIN: return "not ready";
     case MF_ECANCELED: return "canceled";
     case MF_ENOTFOUND: return "not found";
+    case MF_EINVARIANT: return "invariant check failed";
     }
     return "unknown status";
 }
@@ -160,6 +164,11 @@ mf_status mf_context_create(int device, size_t hbm_budget_bytes, mf_context **ou
             if (hipEventCreate(&ev) != hipSuccess) { st = fail(nullptr, MF_EDEVICE, "hipEventCreate failed"); break; }
         for (auto &ev : ctx->pev)
             if (hipEventCreate(&ev) != hipSuccess) { st = fail(nullptr, MF_EDEVICE, "hipEventCreate failed"); break; }
+        for (auto &ev : ctx->sev)
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                st = fail(nullptr, MF_EDEVICE, "hipEventCreate failed");
+                break;
+            }
     } while (0);
     if (st != MF_OK) {
         mf_context_destroy(ctx);
@@ -188,6 +197,8 @@ void mf_context_destroy(mf_context *ctx)
     for (auto ev : ctx->pev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : ctx->bev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto ev : ctx->sev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : ctx->lev) (void)hipEventDestroy(ev);
     for (auto bs : ctx->bstream)
@@ -221,7 +232,40 @@ static mf_status read_ctl(mf_context *ctx, int count = 1)
     return MF_OK;
 }
 
-extern "C" mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_dgraph **out)
+// The library's work on a caller's buffers waits for everything enqueued on
+// the caller's stream so far; afterwards the caller's stream waits for the
+// library's stream.
+static mf_status order_after(mf_context *ctx, mf_stream stream)
+{
+    HIPCHK(ctx, hipEventRecord(ctx->sev[0], (hipStream_t)stream));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->sev[0], 0));
+    return MF_OK;
+}
+static mf_status order_before(mf_context *ctx, mf_stream stream)
+{
+    HIPCHK(ctx, hipEventRecord(ctx->sev[1], ctx->stream));
+    HIPCHK(ctx, hipStreamWaitEvent((hipStream_t)stream, ctx->sev[1], 0));
+    return MF_OK;
+}
+
+static mf_status graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_dgraph **out);
+
+extern "C" mf_status mf_graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_stream stream,
+                                     mf_dgraph **out)
+{
+    if (!ctx || !g || !out) return fail(ctx, MF_EINVAL, "NULL argument");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    mf_status st = MF_OK;
+    if (on_device && (st = order_after(ctx, stream)) != MF_OK) return st;
+    st = graph_upload(ctx, g, on_device, out);
+    if (on_device) {
+        mf_status so = order_before(ctx, stream);
+        if (st == MF_OK) st = so;
+    }
+    return st;
+}
+
+static mf_status graph_upload(mf_context *ctx, const mf_graph *g, int on_device, mf_dgraph **out)
 {
     if (!ctx || !g || !out) return fail(ctx, MF_EINVAL, "NULL argument");
     *out = nullptr;
@@ -330,12 +374,28 @@ extern "C" void mf_graph_free(mf_context *ctx, mf_dgraph *dg)
     delete dg;
 }
 
+static mf_status graph_set_caps(mf_context *ctx, mf_dgraph *dg, const int32_t *cap, int on_device,
+                                int *resumable);
+
 extern "C" mf_status mf_graph_set_caps(mf_context *ctx, mf_dgraph *dg, const int32_t *cap, int on_device,
-                                       int *resumable)
+                                       mf_stream stream, int *resumable)
 {
     if (resumable) *resumable = 0;
     if (!ctx || !dg || (!cap && dg->slots > 0)) return fail(ctx, MF_EINVAL, "NULL argument");
     HIPCHK(ctx, hipSetDevice(ctx->device));
+    mf_status st = MF_OK;
+    if (on_device && (st = order_after(ctx, stream)) != MF_OK) return st;
+    st = graph_set_caps(ctx, dg, cap, on_device, resumable);
+    if (on_device) {
+        mf_status so = order_before(ctx, stream);
+        if (st == MF_OK) st = so;
+    }
+    return st;
+}
+
+static mf_status graph_set_caps(mf_context *ctx, mf_dgraph *dg, const int32_t *cap, int on_device,
+                                int *resumable)
+{
     const int64_t S = dg->slots;
     if (S == 0) {
         if (resumable) *resumable = ctx->warm_dg == dg;
@@ -491,6 +551,8 @@ struct Solve {
     bool profile;
     uint32_t pmask;            // kernels (bits of mf_kernel_id) timed with events under MF_PROFILE
     bool persistent;
+    bool check;                // MF_CHECK_INVARIANTS: state checks after every round and global relabel
+    bool fault_done = false;   // the check_fault_round test hook has fired
     // profiling accumulators
     double ms_dis = 0, ms_mer = 0, ms_gr = 0, ms_phase = 0;
     int64_t n_dis = 0, n_mer = 0, n_gr = 0, n_phase = 0;
@@ -594,6 +656,33 @@ static int td_flags(bool track_deg, int64_t nq)
 {
     constexpr int64_t EAGER_MAX = 16384;
     return (track_deg ? 1 : 0) | (nq <= EAGER_MAX ? 4 : 0);
+}
+
+// MF_CHECK_INVARIANTS: checks the state between rounds (k_check_state).
+static mf_status check_state(Solve &S, int sink, int other, bool after_gr, int64_t rounds)
+{
+    mf_context *ctx = S.ctx;
+    const bool phase1 = sink == S.dg->t;
+    if (phase1 && !S.fault_done && S.opt.check_fault_round > 0 && rounds >= S.opt.check_fault_round &&
+        S.g.slots > 0) {
+        launch_bump(S.st.res, ctx->stream);      // test hook: break the state once
+        S.fault_done = true;
+    }
+    HIPCHK(ctx, hipMemsetAsync(&ctx->ctl->inv_err, 0, sizeof(int32_t), ctx->stream));
+    launch_check_state(S.g, S.st, sink, other, after_gr ? 1 : 0, grid_for(S.g.n, 256, S.maxgrid), ctx->stream);
+    mf_status st = read_ctl(ctx);
+    if (st != MF_OK) return st;
+    const int bits = ctx->ctl_host->inv_err;
+    if (!bits) return MF_OK;
+    static const char *what[] = {"a residual below 0", "res[a] + res[rev a] != cap[a] + cap[rev a]",
+                                 "a push pending between rounds", "an excess != the net inflow of its residuals",
+                                 "an excess below 0 off s", "a label out of range or on a terminal",
+                                 "d(v) > d(w) + 1 on a residual arc after a global relabel",
+                                 "a touched mark left set"};
+    int k = 0;
+    while (!((bits >> k) & 1)) k++;
+    return fail(ctx, MF_EINVARIANT, "invariant broken in phase %d after %lld rounds%s: %s (bits 0x%x)",
+                phase1 ? 1 : 2, (long long)rounds, after_gr ? " and a global relabel" : "", what[k], bits);
 }
 
 static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, int &na, bool &dense)
@@ -788,12 +877,19 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
     int rbatch = 1;              // list rounds per readback: doubles up to 16 while no round stops a batch
     int dbatch = 1;              // dense rounds per readback: doubles up to 8 likewise
     bool list_ready = false;     // the working set is listed in A (else only flagged in act)
+    int64_t checked = 0;         // MF_CHECK_INVARIANTS: rounds whose end state was checked
     while (true) {
+        if (S.check && ps.rounds > checked) {
+            mf_status st = check_state(S, sink, other, false, ps.rounds);
+            if (st != MF_OK) return st;
+            checked = ps.rounds;
+        }
         bool just = false;
         const int64_t gr_thr = o.gr_alpha * n + m + o.gr_level_charge * S.gr_depth;
         if (force || o.gr_freq_num * W > o.gr_freq_den * gr_thr) {
             mf_status st = global_relabel(S, sink, other, ps, na, dense);
             if (st != MF_OK) return st;
+            if (S.check && (st = check_state(S, sink, other, true, ps.rounds)) != MF_OK) return st;
             list_ready = !dense;     // a list-mode working set was compacted from the flags
             rbatch = 1;
             W = 0;
@@ -881,7 +977,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             if (!stopped) {
                 list_ready = true;
                 na = c.na;
-                rbatch = std::min(16, 2 * rbatch);
+                rbatch = S.check ? 1 : std::min(16, 2 * rbatch);
                 continue;
             }
             // the round that stopped the batch: its merge listed the next
@@ -983,7 +1079,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
         list_ready = true;
         if (!stopped) {
             na = c.na;
-            dbatch = std::min(8, 2 * dbatch);
+            dbatch = S.check ? 1 : std::min(8, 2 * dbatch);
             continue;
         }
         // the round that stopped the batch: its merge listed the next
@@ -1171,9 +1267,27 @@ static mf_status solve_small(mf_context *ctx, mf_dgraph *dg, const mf_options &o
     return r.status == 1 ? fail(ctx, MF_ETIMEOUT, "round limit %lld reached", (long long)o.max_rounds) : MF_OK;
 }
 
-extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt,
+static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt, int64_t *value,
+                                int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *ext = nullptr);
+
+extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, mf_stream stream, const mf_options *opt,
                                        int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
                                        mf_stats *stats)
+{
+    if (!ctx || !dg) return fail(ctx, MF_EINVAL, "NULL context or graph");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    mf_status st = order_after(ctx, stream);
+    if (st != MF_OK) return st;
+    st = solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats);
+    mf_status so = order_before(ctx, stream);
+    return st == MF_OK ? so : st;
+}
+
+// ext: a workspace carved by the caller (the no-allocation entry point); then
+// nothing is allocated, the graph is always solved by the grid-wide kernels,
+// and the context's resumable state is left alone.
+static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt, int64_t *value,
+                                int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *ext)
 {
     if (!ctx || !dg) return fail(ctx, MF_EINVAL, "NULL context or graph");
     mf_options o;
@@ -1190,10 +1304,16 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
         return fail(ctx, MF_EINVAL, "no resumable flow of this graph on this context (MF_WARM_START needs a "
                                     "complete solve of it as the context's last solve, and capacities that "
                                     "still hold its flow)");
-    ctx->warm_dg = nullptr;       // the workspace is about to change
+    if ((o.flags & MF_CHECK_INVARIANTS) && (o.flags & MF_PERSISTENT))
+        return fail(ctx, MF_EINVAL, "MF_CHECK_INVARIANTS runs the host-driven rounds: not with MF_PERSISTENT");
+    if (ext && (warm || (o.flags & MF_PROFILE)))
+        return fail(ctx, MF_EINVAL, "MF_WARM_START and MF_PROFILE are not available without allocation");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    if ((st = ensure_workspace(ctx, dg->n, dg->slots)) != MF_OK) return st;
-    if (!warm && !(o.flags & (MF_PERSISTENT | MF_GRID_PATH)) && dg->n <= MF_SMALL_N &&
+    if (!ext) {
+        ctx->warm_dg = nullptr;       // the workspace is about to change
+        if ((st = ensure_workspace(ctx, dg->n, dg->slots)) != MF_OK) return st;
+    }
+    if (!ext && !warm && !(o.flags & (MF_PERSISTENT | MF_GRID_PATH | MF_CHECK_INVARIANTS)) && dg->n <= MF_SMALL_N &&
         dg->slots <= MF_SMALL_SLOTS)
         return solve_small(ctx, dg, o, value, flow_dev, side_dev, stats);
 
@@ -1202,7 +1322,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.ctx = ctx;
     S.dg = dg;
     S.g = dg->view();
-    Workspace &w = ctx->ws;
+    Workspace &w = ext ? *ext : ctx->ws;
     S.st.res = w.res;
     S.st.delta = w.delta;
     S.st.d = w.d;
@@ -1241,6 +1361,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     S.pmask = o.profile_mask ? o.profile_mask : 0xffffffffu;
     S.stride = o.profile_stride > 1 ? o.profile_stride : 1;
     S.persistent = (o.flags & MF_PERSISTENT) != 0;
+    S.check = (o.flags & MF_CHECK_INVARIANTS) != 0;
     if (o.dense_threshold > 0) S.dense_threshold = o.dense_threshold;
 
     const int n = dg->n;
@@ -1287,7 +1408,7 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     if ((st = read_ctl(ctx)) != MF_OK) return st;
     HIPCHK(ctx, hipGetLastError());
     // a complete flow stays in the workspace for a resumed solve
-    if (!preflow_only && !timed_out) ctx->warm_dg = dg;
+    if (!ext && !preflow_only && !timed_out) ctx->warm_dg = dg;
 
     if (value) *value = val;
     if (stats) {
@@ -1351,15 +1472,22 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_
     return timed_out ? fail(ctx, MF_ETIMEOUT, "round limit %lld reached", (long long)o.max_rounds) : MF_OK;
 }
 
-extern "C" mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, const mf_options *opt,
-                                     int64_t *value, int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats)
+extern "C" mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, mf_stream stream,
+                                     const mf_options *opt, int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
+                                     mf_stats *stats)
 {
-    mf_dgraph *dg = nullptr;
-    mf_status st = mf_graph_upload(ctx, dev_g, 1, &dg);
+    if (!ctx || !dev_g) return fail(ctx, MF_EINVAL, "NULL argument");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    mf_status st = order_after(ctx, stream);
     if (st != MF_OK) return st;
-    st = mf_solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats);
-    mf_graph_free(ctx, dg);
-    return st;
+    mf_dgraph *dg = nullptr;
+    st = graph_upload(ctx, dev_g, 1, &dg);
+    if (st == MF_OK) {
+        st = solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats);
+        mf_graph_free(ctx, dg);
+    }
+    mf_status so = order_before(ctx, stream);
+    return st == MF_OK ? so : st;
 }
 
 extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_options *opt,
@@ -1367,7 +1495,7 @@ extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_
 {
     if (!ctx || !host_g) return fail(ctx, MF_EINVAL, "NULL argument");
     mf_dgraph *dg = nullptr;
-    mf_status st = mf_graph_upload(ctx, host_g, 0, &dg);
+    mf_status st = graph_upload(ctx, host_g, 0, &dg);
     if (st != MF_OK) return st;
     int32_t *flow_dev = nullptr;
     uint8_t *side_dev = nullptr;
@@ -1381,7 +1509,7 @@ extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_
         mf_graph_free(ctx, dg);
         return st;
     }
-    st = mf_solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats);
+    st = solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats);
     if (st == MF_OK || st == MF_ETIMEOUT) {
         hipError_t e = hipSuccess;
         if (flow && S) e = hipMemcpy(flow, flow_dev, 4 * S, hipMemcpyDeviceToHost);
