@@ -301,6 +301,26 @@ mf_status mf_solve_device(mf_context *ctx, const mf_graph *dev_g, mf_stream stre
                           int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
                           mf_stats *stats);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the solve of mf_solve_device with no
+ * device allocation and no allocating library call.  The buffers the solve
+ * needs beyond the caller's inputs and outputs (int32 copies of offsets and
+ * reverse slots, and the per-solve state) live in one file-scope device
+ * array of MF_NOALLOC_SCRATCH_BYTES per GPU, held from the first
+ * mf_context_create on that GPU until the process ends; head and cap are
+ * read in place.  A graph that needs more (about 16 bytes per slot plus 51
+ * per vertex, each part rounded up to 256) gets MF_ENOMEM.  Every call on a
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap in time on one GPU (from several threads or contexts) race,
+ * and the caller must not let them.  The context is created beforehand (that
+ * call allocates).  Graphs of any size are solved by the grid-wide kernels;
+ * MF_PROFILE and MF_WARM_START are refused (MF_EINVAL).  Arguments, stream
+ * ordering, outputs and errors otherwise as mf_solve_device. */
+#define MF_NOALLOC_SCRATCH_BYTES (64u << 20)
+mf_status mf_solve_device_noalloc(mf_context *ctx, const mf_graph *dev_g, mf_stream stream,
+                                  const mf_options *opt, int64_t *value, int32_t *flow_dev,
+                                  uint8_t *side_dev, mf_stats *stats);
+
 /* ------------------------------------------------------------------------
  * Batched solver (many instances of uneven size in one launch).
  *

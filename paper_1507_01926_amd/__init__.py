@@ -109,6 +109,7 @@ SIGNATURES = [
     ("mf_solve_uploaded", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("mf_solve_device", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    ("mf_solve_device_noalloc", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     ("mf_batch_solve", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
     ("mf_server_create", ctypes.c_int, [_P, _P, _P]),
     ("mf_server_destroy", None, [_P]),
@@ -283,6 +284,26 @@ class Context:
         st = lib().mf_solve_device(self.h, ctypes.byref(gst), _stream(stream), ctypes.byref(opt or options()),
                                    ctypes.byref(val), None if flow is None else flow.data_ptr(),
                                    None if side is None else side.data_ptr(), ctypes.byref(stats))
+        if st not in allow_status:
+            self._check(st)
+        out = _stats_dict(stats)
+        out.update(status=st, value=int(val.value))
+        return out
+
+    def solve_device_noalloc(self, off, head, rev, cap, s, t, flow=None, side=None,
+                             opt: mf_options | None = None, stream=None, allow_status=()) -> dict:
+        """mf_solve_device_noalloc: as solve_device, with no device allocation
+        (per-solve buffers in the library's fixed scratch array)."""
+        n = int(off.numel()) - 1
+        S = int(head.numel())
+        gst = mf_graph(n, S, off.data_ptr(), head.data_ptr(), rev.data_ptr(), cap.data_ptr(),
+                       int(s), int(t))
+        val = ctypes.c_int64(0)
+        stats = mf_stats()
+        st = lib().mf_solve_device_noalloc(self.h, ctypes.byref(gst), _stream(stream),
+                                           ctypes.byref(opt or options()), ctypes.byref(val),
+                                           None if flow is None else flow.data_ptr(),
+                                           None if side is None else side.data_ptr(), ctypes.byref(stats))
         if st not in allow_status:
             self._check(st)
         out = _stats_dict(stats)

@@ -68,6 +68,7 @@ struct mf_context {
     // of t), from the last grid-path solve; nullptr once anything else has
     // used the workspace
     const mf_dgraph *warm_dg = nullptr;
+    uint8_t *scratch = nullptr;   // device address of the no-allocation scratch array on this device
     int num_cus = 256;
     std::string err;
 };

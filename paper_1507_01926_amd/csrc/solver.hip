@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,6 +78,35 @@ using namespace mf;
 
 thread_local std::string g_global_err;
 
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation entry point (mf_solve_device_noalloc): one
+// file-scope device array per GPU, held from the library's first context on
+// that GPU until the process ends.  Host code never uses its name as an
+// address: mf_context_create looks up the array's device address once per
+// device (with that device current) and every use goes through that address.
+static __device__ __align__(256) uint8_t scratch[MF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_addr[MAX_DEVICES] = {};   // device address of `scratch` on each device
+}
+
+// Called with `device` current.
+static mf_status scratch_lookup(int device, uint8_t **out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return fail(nullptr, MF_EINVAL, "device %d beyond the table", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, MF_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_addr[device] = (uint8_t *)p;
+    }
+    *out = g_scratch_addr[device];
+    return MF_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Public helpers
@@ -169,6 +199,7 @@ mf_status mf_context_create(int device, size_t hbm_budget_bytes, mf_context **ou
                 st = fail(nullptr, MF_EDEVICE, "hipEventCreate failed");
                 break;
             }
+        if (st == MF_OK) st = scratch_lookup(device, &ctx->scratch);
     } while (0);
     if (st != MF_OK) {
         mf_context_destroy(ctx);
@@ -1520,6 +1551,118 @@ extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_
     dfree(ctx, side_dev, N);
     mf_graph_free(ctx, dg);
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// The solve of mf_solve_device without device allocation
+
+// Byte offsets of the graph copies and the per-solve state inside the
+// scratch array; returns the bytes needed.
+struct ScratchLayout {
+    size_t off, rev, res, delta, C, d, dn, owner, e, act, side, touched, A, A2, Q, Q2, H, end;
+};
+static ScratchLayout scratch_layout(int64_t n, int64_t slots)
+{
+    ScratchLayout L;
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p += align256(bytes ? bytes : 4);
+        return at;
+    };
+    const size_t N = (size_t)n, S = (size_t)std::max<int64_t>(slots, 1);
+    L.off = take(4 * (N + 1));
+    L.rev = take(4 * S);
+    L.res = take(4 * S);
+    L.delta = take(4 * S);
+    L.C = take(4 * (S + N));
+    L.d = take(4 * N);
+    L.dn = take(4 * N);
+    L.owner = take(4 * N);
+    L.e = take(8 * N);
+    L.act = take(N);
+    L.side = take(N);
+    L.touched = take(N);
+    L.A = take(4 * N);
+    L.A2 = take(4 * N);
+    L.Q = take(4 * N);
+    L.Q2 = take(4 * N);
+    L.H = take(4 * N);
+    L.end = p;
+    return L;
+}
+
+extern "C" mf_status mf_solve_device_noalloc(mf_context *ctx, const mf_graph *g, mf_stream stream,
+                                             const mf_options *opt, int64_t *value, int32_t *flow_dev,
+                                             uint8_t *side_dev, mf_stats *stats)
+{
+    if (!ctx || !g) return fail(ctx, MF_EINVAL, "NULL argument");
+    if (g->n < 2) return fail(ctx, MF_EINVAL, "n must be at least 2");
+    if (g->slots < 0 || g->slots >= 2147483647LL || (int64_t)g->n + g->slots >= 2147483647LL)
+        return fail(ctx, MF_EINVAL, "slots out of the supported range");
+    if (g->s < 0 || g->s >= g->n || g->t < 0 || g->t >= g->n || g->s == g->t)
+        return fail(ctx, MF_EINVAL, "s and t must be distinct vertices");
+    if (!g->offsets || (g->slots > 0 && (!g->head || !g->rev || !g->cap)))
+        return fail(ctx, MF_EINVAL, "NULL graph array");
+    const ScratchLayout L = scratch_layout(g->n, g->slots);
+    if (L.end > (size_t)MF_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, MF_ENOMEM, "the graph needs %zu bytes of scratch; the no-allocation entry point has %zu",
+                    L.end, (size_t)MF_NOALLOC_SCRATCH_BYTES);
+    if (!ctx->scratch) return fail(ctx, MF_EDEVICE, "no scratch address for device %d", ctx->device);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    mf_status st = order_after(ctx, stream);
+    if (st != MF_OK) return st;
+    uint8_t *base = ctx->scratch;
+    // residency step into the scratch: int32 offsets and reverse slots;
+    // heads and capacities are read where the caller keeps them
+    mf_dgraph dg;
+    dg.n = g->n;
+    dg.s = g->s;
+    dg.t = g->t;
+    dg.slots = g->slots;
+    dg.off = (int32_t *)(base + L.off);
+    dg.rev = (int32_t *)(base + L.rev);
+    dg.head = const_cast<int32_t *>(g->head);
+    dg.cap = const_cast<int32_t *>(g->cap);
+    const int maxg = ctx->num_cus * 8;
+    HIPCHK(ctx, hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
+    launch_narrow(g->offsets, g->rev, dg.off, dg.rev, dg.n, dg.slots, ctx->ctl,
+                  grid_for(std::max<int64_t>(dg.slots, (int64_t)dg.n + 1), 256, maxg), ctx->stream);
+    if ((st = read_ctl(ctx)) != MF_OK) return st;
+    if (ctx->ctl_host->err == 0) {
+        launch_validate(dg.view(), ctx->ctl, grid_for(dg.slots, 256, maxg), ctx->stream);
+        launch_degree_stats(dg.view(), ctx->ctl, grid_for(dg.n, 256, maxg), ctx->stream);
+        if ((st = read_ctl(ctx)) != MF_OK) return st;
+    }
+    if (ctx->ctl_host->err) {
+        const int bits = ctx->ctl_host->err;
+        (void)order_before(ctx, stream);
+        return fail(ctx, MF_EINVAL, "invalid graph: %s", validation_message(bits));
+    }
+    dg.maxdeg_inner = ctx->ctl_host->maxdeg_inner;
+    dg.deg_s = ctx->ctl_host->deg_s;
+    dg.deg_t = ctx->ctl_host->deg_t;
+    Workspace w;
+    w.n_cap = g->n;
+    w.s_cap = std::max<int64_t>(g->slots, 1);
+    w.res = (int32_t *)(base + L.res);
+    w.delta = (int32_t *)(base + L.delta);
+    w.C = (int32_t *)(base + L.C);
+    w.d = (int32_t *)(base + L.d);
+    w.dn = (int32_t *)(base + L.dn);
+    w.owner = (int32_t *)(base + L.owner);
+    w.e = (int64_t *)(base + L.e);
+    w.act = base + L.act;
+    w.side = base + L.side;
+    w.touched = base + L.touched;
+    w.A = (int32_t *)(base + L.A);
+    w.A2 = (int32_t *)(base + L.A2);
+    w.Q = (int32_t *)(base + L.Q);
+    w.Q2 = (int32_t *)(base + L.Q2);
+    w.H = (int32_t *)(base + L.H);
+    st = solve_uploaded(ctx, &dg, opt, value, flow_dev, side_dev, stats, &w);
+    mf_status so = order_before(ctx, stream);
+    return st == MF_OK ? so : st;
 }
 
 // ---------------------------------------------------------------------------
