@@ -122,6 +122,7 @@ typedef struct {
                                   distances are valid labels, Sec. 2.1).  Rounds run one per
                                   read-back in this mode, and the grid-wide kernels solve
                                   every graph */
+#define MF_BATCH_GRID_SLOTS 262144
 #define MF_SMALL_N      8192
 #define MF_SMALL_SLOTS  16384
 
@@ -157,6 +158,10 @@ typedef struct {
     int32_t check_fault_round;   /* test hook for MF_CHECK_INVARIANTS (0 = off): after this many
                                     rounds of phase 1 the host raises one residual by 1 before the
                                     check runs, which must then stop the solve with MF_EINVARIANT */
+    int32_t batch_grid_slots;    /* batched and served forms: an instance with more slots than this
+                                    is solved by the grid-wide kernels (one instance at a time, the
+                                    whole device) instead of one workgroup (0 = MF_BATCH_GRID_SLOTS) */
+    int32_t reserved;
 } mf_options;
 
 typedef struct {
@@ -340,10 +345,16 @@ typedef struct {
                                     and checking the graph, and device time of the whole
                                     request (pull, checks, solve, results sent back) */
     double ms_latency;           /* server: time from mf_server_submit to the result being ready */
+    int32_t resumed;             /* server re-solve of a resident graph: 1 if it continued from the
+                                    graph's previous flow, 0 if it started from zero flow */
+    int32_t reserved;
 } mf_result;
 
 /* Solves k graphs given in host memory, each by the method of
- * mf_solve_uploaded (Sec. 2, 2.1, 3.1).  opts is NULL (the defaults for all)
+ * mf_solve_uploaded (Sec. 2, 2.1, 3.1).  Instances up to the routing size
+ * (mf_options.batch_grid_slots) run in the persistent batch launch; larger
+ * ones are solved after it, one at a time, by the grid-wide kernels (their
+ * lanes_per_vertex result is 0).  opts is NULL (the defaults for all)
  * or an array of k options (per-instance schedules, e.g. from the autotuner;
  * lanes_per_vertex 0 = automatic, otherwise 4, 8, 16 or 32).  flows[i] /
  * sides[i] are host buffers (int32[slots_i] / uint8[n_i]) or NULL, and flows
@@ -361,7 +372,10 @@ mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *graphs, con
  * in device memory until it is solved, and runs admitted requests with
  * continuous batching (a request joins the running persistent kernel as soon
  * as a workgroup is free; that workgroup pulls the graph from pinned host
- * memory and sends the results back itself).  Results are identical to
+ * memory and sends the results back itself).  A request with more slots than
+ * the routing size (mf_options.batch_grid_slots) goes to a second lane that
+ * solves one request at a time with the grid-wide kernels, beside the
+ * persistent kernel, in a slice of the same budget.  Results are identical to
  * mf_solve's for the same options.  All server calls are thread-safe.
  */
 typedef struct {
@@ -404,6 +418,26 @@ mf_status mf_server_wait(mf_server *srv, uint64_t ticket, int64_t timeout_ms, mf
  * one completes with MF_ECANCELED when its solve ends. */
 mf_status mf_server_cancel(mf_server *srv, uint64_t ticket);
 mf_status mf_server_get_stats(mf_server *srv, mf_server_stats *out);
+
+/* Resident graphs: re-solves after capacity changes (the vision and
+ * partitioning inputs of Sec. 4.1 are solved again and again with new
+ * capacities).  mf_server_register_graph copies the graph (host pointers)
+ * into the server's device region, checks it as mf_graph_upload does, and
+ * returns an id once it is resident (MF_EINVAL: invalid graph; MF_ENOMEM:
+ * larger than the budget).  mf_server_submit_caps queues a solve of that
+ * graph with new capacities cap[slots] (host, copied; checked as
+ * mf_graph_set_caps does, an invalid one completes with MF_EINVAL): the
+ * capacities replace the graph's, and the solve continues from the flow of
+ * the graph's previous complete solve when every new capacity still holds
+ * it (out->resumed = 1), else it starts from zero flow.  Value, cut and sink
+ * side are those of the graph with the new capacities either way.
+ * Requests for one graph run in submission order, by the server's grid-wide
+ * lane.  mf_server_release_graph frees the graph once no queued request names
+ * it (MF_ENOTFOUND: unknown id). */
+mf_status mf_server_register_graph(mf_server *srv, const mf_graph *host_g, uint64_t *graph_id);
+mf_status mf_server_submit_caps(mf_server *srv, uint64_t graph_id, const int32_t *cap, const mf_options *opt,
+                                int want_flow, uint64_t *ticket);
+mf_status mf_server_release_graph(mf_server *srv, uint64_t graph_id);
 
 #ifdef __cplusplus
 }

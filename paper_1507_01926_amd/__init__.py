@@ -51,7 +51,8 @@ class mf_options(ctypes.Structure):
                 ("lanes_per_merge", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_bfs", ctypes.c_int32),
                 ("profile_mask", ctypes.c_uint32), ("bfs_bottom_up_factor", ctypes.c_int32),
-                ("profile_stride", ctypes.c_int32), ("check_fault_round", ctypes.c_int32)]
+                ("profile_stride", ctypes.c_int32), ("check_fault_round", ctypes.c_int32),
+                ("batch_grid_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mf_stats(ctypes.Structure):
@@ -76,7 +77,8 @@ class mf_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("lanes_per_vertex", ctypes.c_int32)] + [
         (k, ctypes.c_int64) for k in ("value", "cut_capacity", "rounds", "rounds2", "global_relabels",
                                       "global_relabels2", "bfs_levels", "pushes", "relabels")] + [
-        ("ms_start", ctypes.c_double), ("ms_end", ctypes.c_double), ("ms_latency", ctypes.c_double)]
+        ("ms_start", ctypes.c_double), ("ms_end", ctypes.c_double), ("ms_latency", ctypes.c_double),
+        ("resumed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mf_server_config(ctypes.Structure):
@@ -118,6 +120,9 @@ SIGNATURES = [
     ("mf_server_wait", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int64, _P, _P, _P]),
     ("mf_server_cancel", ctypes.c_int, [_P, ctypes.c_uint64]),
     ("mf_server_get_stats", ctypes.c_int, [_P, _P]),
+    ("mf_server_register_graph", ctypes.c_int, [_P, _P, _P]),
+    ("mf_server_submit_caps", ctypes.c_int, [_P, ctypes.c_uint64, _P, _P, ctypes.c_int, _P]),
+    ("mf_server_release_graph", ctypes.c_int, [_P, ctypes.c_uint64]),
 ]
 
 
@@ -436,6 +441,36 @@ class Server:
         d["flow"] = None if flow is None else flow[:S]
         d["sink_side"] = side
         return d
+
+    def register_graph(self, g) -> int:
+        """mf_server_register_graph: keep `g` resident for re-solves with new capacities."""
+        hg = _HostGraph(g)
+        gid = ctypes.c_uint64()
+        st = lib().mf_server_register_graph(self.h, ctypes.byref(hg.st), ctypes.byref(gid))
+        if st != MF_OK:
+            raise MaxflowError(st, "register failed")
+        self._graphs = getattr(self, "_graphs", {})
+        self._graphs[gid.value] = (g.n, hg.head.shape[0])
+        return gid.value
+
+    def submit_caps(self, graph_id: int, cap, opt: mf_options | None = None, want_flow: bool = True) -> int:
+        """mf_server_submit_caps: re-solve a resident graph with capacities `cap` (int32[slots])."""
+        n, S = self._graphs[graph_id]
+        c = np.ascontiguousarray(cap, dtype=np.int32)
+        if c.shape[0] != S:
+            raise ValueError("cap must have one entry per slot")
+        t = ctypes.c_uint64()
+        st = lib().mf_server_submit_caps(self.h, ctypes.c_uint64(graph_id), c.ctypes.data,
+                                         None if opt is None else ctypes.byref(opt), int(want_flow), ctypes.byref(t))
+        if st != MF_OK:
+            raise MaxflowError(st, "submit_caps failed")
+        self._shapes[t.value] = (n, S, want_flow)
+        return t.value
+
+    def release_graph(self, graph_id: int):
+        st = lib().mf_server_release_graph(self.h, ctypes.c_uint64(graph_id))
+        if st != MF_OK:
+            raise MaxflowError(st, "release failed")
 
     def poll(self, ticket: int):
         return self._collect(lib().mf_server_poll, ticket)

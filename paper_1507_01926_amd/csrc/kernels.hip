@@ -245,8 +245,17 @@ __global__ void k_bump(int32_t *p) { *p += 1; }
 __global__ void k_gr_init(GraphView g, StateView st, int sink)
 {
     const int stride = gridDim.x * blockDim.x;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int v = tid; v < g.n; v += stride) {
         st.d[v] = v == sink ? 0 : g.n;        // dn follows in k_gr_rebuild
+    }
+    if (st.hr) {
+        // the residuals do not change during the relabel: pack "w can send
+        // to v" (res of the reverse slot > 0) beside each slot's head
+        for (int a = tid; a < g.slots; a += stride) {
+            const int w = g.head[a];
+            st.hr[a] = st.res[g.rev[a]] > 0 ? (int)((unsigned)w | 0x80000000u) : w;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.Q[0] = sink;
@@ -323,12 +332,17 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
                 bool claim = false;
                 int w = 0;
                 if (a < end) {
-                    w = g.head[a];
                     bool open;
-                    if (flags & TD_EAGER) {
+                    if (st.hr) {
+                        const int x = st.hr[a];
+                        w = x & 0x7fffffff;
+                        open = x < 0 && st.d[w] == g.n;
+                    } else if (flags & TD_EAGER) {
+                        w = g.head[a];
                         const int r = st.res[g.rev[a]];
                         open = st.d[w] == g.n && r > 0;
                     } else {
+                        w = g.head[a];
                         open = st.d[w] == g.n && st.res[g.rev[a]] > 0;
                     }
                     if (open && w != sink && w != other && atomicCAS(&st.d[w], g.n, next) == g.n) {
@@ -389,8 +403,16 @@ __global__ __launch_bounds__(256) void k_gr_hub(GraphView g, StateView st, int l
             bool claim = false;
             int w = 0;
             if (a < end) {
-                w = g.head[a];
-                if (w != sink && w != other && st.d[w] == g.n && st.res[g.rev[a]] > 0) {
+                bool open;
+                if (st.hr) {
+                    const int x = st.hr[a];
+                    w = x & 0x7fffffff;
+                    open = x < 0;
+                } else {
+                    w = g.head[a];
+                    open = st.res[g.rev[a]] > 0;
+                }
+                if (open && w != sink && w != other && st.d[w] == g.n) {
                     if (atomicCAS(&st.d[w], g.n, next) == g.n) {
                         claim = true;
                         if (track_deg) cdeg += g.off[w + 1] - g.off[w];

@@ -83,6 +83,12 @@ struct StateView {
     int32_t *A, *A2;       // working-set lists (current, next)
     int32_t *C;            // candidate list (vertices touched in the round)
     int32_t *Q, *Q2;       // BFS frontiers
+    // hr[a] = head[a] with bit 31 set iff the reverse slot holds residual
+    // capacity (res[rev a] > 0), rebuilt at the start of each global relabel:
+    // a top-down level then reads one coalesced word per slot (each edge
+    // carries its reverse edge's residual, the representation of Sec. 4.2).
+    // Null where not provided; the levels then gather res[rev a].
+    int32_t *hr;
     Ctl *ctl;
 };
 

@@ -44,6 +44,7 @@ struct Workspace {
     int64_t *e = nullptr;
     uint8_t *act = nullptr, *side = nullptr, *touched = nullptr;
     int32_t *A = nullptr, *A2 = nullptr, *C = nullptr, *Q = nullptr, *Q2 = nullptr, *H = nullptr;
+    int32_t *hr = nullptr;   // packed heads of the top-down search (null: gather reverse residuals)
     size_t bytes = 0;
 };
 
@@ -134,12 +135,13 @@ inline void dfree(mf_context *ctx, void *p, size_t bytes)
 
 struct InstLayout {
     size_t off, head, rev, cap, res, delta, C, d, dn, owner, A, A2, Q, Q2, H, e, act, touched, side, flow;
+    size_t hr;         // packed heads of the top-down search (grid-wide kernels only; 0 = none)
     size_t end;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-inline InstLayout layout_for(size_t base, int64_t n, int64_t S, bool want_flow)
+inline InstLayout layout_for(size_t base, int64_t n, int64_t S, bool want_flow, bool with_hr = false)
 {
     InstLayout L;
     size_t p = base;
@@ -168,9 +170,57 @@ inline InstLayout layout_for(size_t base, int64_t n, int64_t S, bool want_flow)
     L.touched = take(n);
     L.side = take(n);
     L.flow = want_flow ? take(4 * S) : 0;
+    L.hr = with_hr ? take(4 * S) : 0;
     L.end = p;
     return L;
 }
+
+// The per-solve state of the grid-wide kernels over an instance's slice.
+inline Workspace workspace_in(uint8_t *base, const InstLayout &L, int64_t n, int64_t S)
+{
+    Workspace w;
+    w.n_cap = n;
+    w.s_cap = std::max<int64_t>(S, 1);
+    w.res = (int32_t *)(base + L.res);
+    w.delta = (int32_t *)(base + L.delta);
+    w.C = (int32_t *)(base + L.C);
+    w.d = (int32_t *)(base + L.d);
+    w.dn = (int32_t *)(base + L.dn);
+    w.owner = (int32_t *)(base + L.owner);
+    w.e = (int64_t *)(base + L.e);
+    w.act = base + L.act;
+    w.side = base + L.side;
+    w.touched = base + L.touched;
+    w.A = (int32_t *)(base + L.A);
+    w.A2 = (int32_t *)(base + L.A2);
+    w.Q = (int32_t *)(base + L.Q);
+    w.Q2 = (int32_t *)(base + L.Q2);
+    w.H = (int32_t *)(base + L.H);
+    w.hr = L.hr ? (int32_t *)(base + L.hr) : nullptr;
+    return w;
+}
+
+// Batched and served forms: an instance with more slots than this is solved
+// by the grid-wide kernels instead of one workgroup.
+inline int64_t batch_grid_slots(const mf_options &o)
+{
+    return o.batch_grid_slots > 0 ? (int64_t)o.batch_grid_slots : (int64_t)MF_BATCH_GRID_SLOTS;
+}
+
+// Solver entry points shared with the server (solver.hip).
+//  solve_in_workspace: the solve of mf_solve_uploaded over a caller-carved
+//    workspace (nothing allocated, grid-wide kernels); with resume, the
+//    workspace already holds the residuals of a complete flow of this graph
+//    and e(t) its value, and the solve continues from that flow.
+//  upload_graph_into: copies a host graph into a caller-carved slice
+//    (stage64: device int64 scratch of 8(n+1) + 8 slots bytes), narrows and
+//    checks it on the context's stream, and fills *dg.
+mf_status solve_in_workspace(mf_context *ctx, mf_dgraph *dg, const mf_options *opt, int64_t *value,
+                             int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *w, bool resume);
+mf_status upload_graph_into(mf_context *ctx, const mf_graph *host_g, uint8_t *base, const InstLayout &L,
+                            int64_t *stage64, mf_dgraph *dg);
+mf_status check_caps_into(mf_context *ctx, mf_dgraph *dg, const int32_t *cap_host, int32_t *tmp_dev,
+                          int32_t *keep_res, bool has_flow, bool *resumable);
 
 inline int batch_lanes(int requested, int64_t n, int64_t S)
 {

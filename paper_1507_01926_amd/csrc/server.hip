@@ -22,6 +22,16 @@
 // by the kernel's own loads and stores over PCIe, so a kernel that keeps
 // every compute unit busy never waits for a copy queued behind it.
 // Graphs and residual state stay in device memory for the whole solve.
+//
+// Grid lane.  A request above the routing size (batch_grid_slots: one
+// workgroup would take seconds on it) and every re-solve of a resident graph
+// go to a second worker with a context of its own, which solves them one at
+// a time with the grid-wide kernels in a slice of the same device region,
+// beside the serve kernel.  A resident graph (mf_server_register_graph)
+// keeps its arrays and the residuals of its last complete solve in its
+// slice; a re-solve with new capacities (mf_server_submit_caps) resumes
+// from that flow when every new capacity still holds it (the warm start of
+// the plain solver), and starts from zero flow otherwise.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -91,9 +101,29 @@ class RegionAllocator {
 };
 
 enum ReqState { STAGING, PENDING, ADMITTING, PUBLISHED, COMPLETE };
+enum ReqKind { SOLVE, REGISTER, RESOLVE };
+
+// A graph kept in the device region for re-solves (grid lane).
+struct Resident {
+    uint64_t id = 0;
+    int32_t n = 0, s = 0, t = 0;
+    int64_t S = 0;
+    size_t off = 0, bytes = 0;       // slice of the region
+    InstLayout lay;                  // graph, state, flow, side
+    size_t keep = 0;                 // region offset of the kept residuals (int32[S])
+    bool valid = false;              // the graph was uploaded and checked
+    bool has_flow = false;           // keep holds the residuals of a complete solve
+    int64_t value = 0;               // its flow value
+    bool released = false;
+    int pending = 0;                 // queued requests that name it
+    int32_t maxdeg_inner = 0, deg_s = 0, deg_t = 0;   // degree figures (the structure never changes)
+};
 
 struct Request {
     uint64_t ticket = 0;
+    ReqKind kind = SOLVE;
+    bool grid = false;           // solved by the grid lane
+    uint64_t graph_id = 0;       // REGISTER / RESOLVE: the resident graph
     int32_t n = 0, s = 0, t = 0;
     int64_t S = 0;
     std::vector<int64_t> off, rev;
@@ -139,6 +169,29 @@ HostLayout host_layout(int64_t n, int64_t S)
     return h;
 }
 
+// Device slice of a request solved by the grid lane: the instance layout
+// (with the packed heads of the top-down search), then int64 staging for the
+// offsets and reverse slots during the upload.
+struct GridSlice {
+    InstLayout lay;
+    size_t stage, keep, end;
+};
+GridSlice grid_slice(int64_t n, int64_t S, bool want_flow, bool resident)
+{
+    GridSlice g;
+    g.lay = layout_for(0, n, S, want_flow || resident, true);
+    size_t p = g.lay.end;
+    g.keep = 0;
+    if (resident) {
+        g.keep = p;
+        p = align256(p + std::max<size_t>(4 * (size_t)S, 4));
+    }
+    g.stage = p;
+    p = align256(p + 8 * (size_t)(n + 1) + 8 * (size_t)S);
+    g.end = p;
+    return g;
+}
+
 }  // namespace
 
 struct mf_server {
@@ -169,9 +222,19 @@ struct mf_server {
     mf_server_stats st;
     size_t bytes_in_use = 0;
     std::string err;
+    // grid lane
+    mf_context *gctx = nullptr;
+    std::thread gworker;
+    std::deque<Request *> gpending;
+    std::mutex amu;                   // guards `alloc` (both workers carve the region)
+    std::condition_variable acv;      // region space freed
+    std::unordered_map<uint64_t, Resident *> residents;
+    uint64_t next_graph = 1;
+    int grid_busy = 0;                // a grid-lane request is being solved
 };
 
 static void server_loop(mf_server *sv);
+static void grid_loop(mf_server *sv);
 
 // Gives back what a request that will not be admitted holds on the host
 // side (called with the lock held).
@@ -239,7 +302,9 @@ extern "C" mf_status mf_server_create(mf_context *ctx, const mf_server_config *c
         return bail(MF_EDEVICE, "device counter allocation failed");
     sv->idle_ticks = ctx->wall_hz / 1000ull * (uint64_t)sv->cfg.idle_ms;
     for (int q = 0; q < 4; q++) sv->slot_owner[q].assign(SERVE_CAP, nullptr);
+    if (mf_context_create(ctx->device, 0, &sv->gctx) != MF_OK) return bail(MF_EDEVICE, "grid-lane context failed");
     sv->worker = std::thread(server_loop, sv);
+    sv->gworker = std::thread(grid_loop, sv);
     *out = sv;
     return MF_OK;
 }
@@ -247,11 +312,13 @@ extern "C" mf_status mf_server_create(mf_context *ctx, const mf_server_config *c
 extern "C" void mf_server_destroy(mf_server *sv)
 {
     if (!sv) return;
-    if (sv->worker.joinable()) {
-        sv->stop = true;
-        sv->cv.notify_all();
-        sv->worker.join();
-    }
+    sv->stop = true;
+    sv->cv.notify_all();
+    sv->acv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    if (sv->gworker.joinable()) sv->gworker.join();
+    if (sv->gctx) mf_context_destroy(sv->gctx);
+    for (auto &kv : sv->residents) delete kv.second;
     (void)hipSetDevice(sv->ctx->device);
     for (int q = 0; q < 4; q++)
         if (sv->hq[q]) __atomic_store_n(&sv->hq[q]->shutdown, 1, __ATOMIC_RELEASE);
@@ -292,8 +359,14 @@ extern "C" mf_status mf_server_submit(mf_server *sv, const mf_graph *g, const mf
     if (shape_ok) {
         r->G = batch_lanes(o.lanes_per_vertex, g->n, g->slots);
         r->queue = 0;        // one queue; the serve kernel handles every lane count
-        r->bytes = request_bytes(g->n, g->slots, r->want_flow);
-        r->host_bytes = host_layout(g->n, g->slots).end;
+        r->grid = g->slots > batch_grid_slots(o);
+        if (r->grid) {
+            r->bytes = grid_slice(g->n, g->slots, r->want_flow, false).end;
+            r->host_bytes = 0;
+        } else {
+            r->bytes = request_bytes(g->n, g->slots, r->want_flow);
+            r->host_bytes = host_layout(g->n, g->slots).end;
+        }
     }
     const bool fits = shape_ok && r->bytes <= sv->cfg.hbm_budget_bytes && r->host_bytes <= sv->harena_bytes;
     {
@@ -315,9 +388,12 @@ extern "C" mf_status mf_server_submit(mf_server *sv, const mf_graph *g, const mf
         // no earlier request is still waiting for one; otherwise into
         // pageable memory, and the worker stages it at admission.  Pending
         // requests stay in ticket order, so those holding a slice always
-        // precede those waiting for one.
+        // precede those waiting for one.  Grid-lane requests keep their copy
+        // in pageable memory.
         r->state = STAGING;
-        if (sv->unstaged == 0 && sv->halloc.alloc(r->host_bytes, r->host_off))
+        if (r->grid)
+            ;
+        else if (sv->unstaged == 0 && sv->halloc.alloc(r->host_bytes, r->host_off))
             r->staged = true;
         else
             sv->unstaged++;
@@ -340,10 +416,121 @@ extern "C" mf_status mf_server_submit(mf_server *sv, const mf_graph *g, const mf
         sv->st.canceled++;
     } else {
         r->state = PENDING;
-        auto pos = sv->pending.end();
-        while (pos != sv->pending.begin() && (*(pos - 1))->ticket > r->ticket) --pos;
-        sv->pending.insert(pos, r);
+        auto &q = r->grid ? sv->gpending : sv->pending;
+        auto pos = q.end();
+        while (pos != q.begin() && (*(pos - 1))->ticket > r->ticket) --pos;
+        q.insert(pos, r);
     }
+    sv->cv.notify_all();
+    return MF_OK;
+}
+
+// Resident graphs (grid lane).  Registration is processed by the grid
+// worker in queue order and waited for here.
+extern "C" mf_status mf_server_register_graph(mf_server *sv, const mf_graph *g, uint64_t *graph_id)
+{
+    if (!sv || !g || !graph_id) return MF_EINVAL;
+    const bool shape_ok = g->n >= 2 && g->slots >= 0 && g->slots < 2147483647LL &&
+                          (int64_t)g->n + g->slots < 2147483647LL && g->s >= 0 && g->s < g->n && g->t >= 0 &&
+                          g->t < g->n && g->s != g->t && g->offsets && (g->slots == 0 || (g->head && g->rev && g->cap));
+    if (!shape_ok) return MF_EINVAL;
+    const size_t bytes = grid_slice(g->n, g->slots, true, true).end;
+    if (bytes > sv->cfg.hbm_budget_bytes) return MF_ENOMEM;
+    Request *r = new (std::nothrow) Request();
+    Resident *res = new (std::nothrow) Resident();
+    if (!r || !res) {
+        delete r;
+        delete res;
+        return MF_ENOMEM;
+    }
+    mf_options_default(&r->opt);
+    r->kind = REGISTER;
+    r->grid = true;
+    r->n = g->n;
+    r->s = g->s;
+    r->t = g->t;
+    r->S = g->slots;
+    r->bytes = bytes;
+    r->off.assign(g->offsets, g->offsets + g->n + 1);
+    r->rev.assign(g->rev, g->rev + g->slots);
+    r->head.assign(g->head, g->head + g->slots);
+    r->cap.assign(g->cap, g->cap + g->slots);
+    memset(&r->result, 0, sizeof r->result);
+    res->n = g->n;
+    res->s = g->s;
+    res->t = g->t;
+    res->S = g->slots;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    res->id = sv->next_graph++;
+    r->graph_id = res->id;
+    res->pending = 1;
+    sv->residents[res->id] = res;
+    r->ticket = sv->next_ticket++;
+    r->t_submit = Clock::now();
+    r->state = PENDING;
+    sv->reqs[r->ticket] = r;
+    sv->gpending.push_back(r);
+    sv->cv.notify_all();
+    while (r->state != COMPLETE) sv->cv.wait(lk);
+    const mf_status st = (mf_status)r->result.status;
+    sv->reqs.erase(r->ticket);
+    delete r;
+    if (st != MF_OK) {
+        sv->residents.erase(res->id);
+        delete res;
+        return st;
+    }
+    *graph_id = res->id;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_server_submit_caps(mf_server *sv, uint64_t graph_id, const int32_t *cap,
+                                           const mf_options *opt, int want_flow, uint64_t *ticket)
+{
+    if (!sv || !ticket) return MF_EINVAL;
+    Request *r = new (std::nothrow) Request();
+    if (!r) return MF_ENOMEM;
+    if (opt) r->opt = *opt; else mf_options_default(&r->opt);
+    r->kind = RESOLVE;
+    r->grid = true;
+    r->graph_id = graph_id;
+    r->want_flow = want_flow != 0 && !(r->opt.flags & MF_PREFLOW_ONLY);
+    memset(&r->result, 0, sizeof r->result);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->residents.find(graph_id);
+    if (it == sv->residents.end() || it->second->released) {
+        delete r;
+        return MF_ENOTFOUND;
+    }
+    Resident *res = it->second;
+    if (!cap && res->S > 0) {
+        delete r;
+        return MF_EINVAL;
+    }
+    r->n = res->n;
+    r->s = res->s;
+    r->t = res->t;
+    r->S = res->S;
+    if (res->S) r->cap.assign(cap, cap + res->S);
+    res->pending++;
+    r->ticket = sv->next_ticket++;
+    r->t_submit = Clock::now();
+    r->state = PENDING;
+    sv->reqs[r->ticket] = r;
+    sv->st.submitted++;
+    sv->gpending.push_back(r);
+    *ticket = r->ticket;
+    sv->cv.notify_all();
+    return MF_OK;
+}
+
+extern "C" mf_status mf_server_release_graph(mf_server *sv, uint64_t graph_id)
+{
+    if (!sv) return MF_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->residents.find(graph_id);
+    if (it == sv->residents.end() || it->second->released) return MF_ENOTFOUND;
+    it->second->released = true;     // the grid worker frees it once no request names it
     sv->cv.notify_all();
     return MF_OK;
 }
@@ -405,6 +592,24 @@ extern "C" mf_status mf_server_cancel(mf_server *sv, uint64_t ticket)
     Request *r = it->second;
     if (r->state == COMPLETE) return MF_OK;
     r->canceled = true;    // STAGING, ADMITTING or PUBLISHED: completes as canceled when that step ends
+    if (r->state == PENDING && r->grid) {
+        if (r->kind == REGISTER) return MF_OK;     // registration is waited for by its caller
+        for (auto p = sv->gpending.begin(); p != sv->gpending.end(); ++p)
+            if (*p == r) {
+                sv->gpending.erase(p);
+                break;
+            }
+        if (r->kind == RESOLVE) {
+            auto it2 = sv->residents.find(r->graph_id);
+            if (it2 != sv->residents.end()) it2->second->pending--;
+        }
+        r->result.status = MF_ECANCELED;
+        r->state = COMPLETE;
+        r->t_done = Clock::now();
+        sv->st.canceled++;
+        sv->cv.notify_all();
+        return MF_OK;
+    }
     if (r->state == PENDING) {
         for (auto p = sv->pending.begin(); p != sv->pending.end(); ++p)
             if (*p == r) {
@@ -426,8 +631,8 @@ extern "C" mf_status mf_server_get_stats(mf_server *sv, mf_server_stats *out)
     if (!sv || !out) return MF_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     *out = sv->st;
-    out->inflight = (int64_t)sv->inflight_list.size();
-    out->queued = (int64_t)sv->pending.size();
+    out->inflight = (int64_t)sv->inflight_list.size() + sv->grid_busy;
+    out->queued = (int64_t)sv->pending.size() + (int64_t)sv->gpending.size();
     out->bytes_in_use = sv->bytes_in_use;
     return MF_OK;
 }
@@ -465,7 +670,10 @@ static bool admit(mf_server *sv, Request *r)
     const int q = r->queue;
     const int32_t index = sv->published[q];
     if (sv->slot_owner[q][index % SERVE_CAP]) return false;
-    if (!sv->alloc.alloc(r->bytes, off)) return false;
+    {
+        std::lock_guard<std::mutex> la(sv->amu);
+        if (!sv->alloc.alloc(r->bytes, off)) return false;
+    }
     if (!r->staged) {
         bool got;
         {
@@ -473,6 +681,7 @@ static bool admit(mf_server *sv, Request *r)
             got = sv->halloc.alloc(r->host_bytes, r->host_off);
         }
         if (!got) {
+            std::lock_guard<std::mutex> la(sv->amu);
             sv->alloc.release(off, r->bytes);
             return false;
         }
@@ -583,7 +792,11 @@ static void finish(mf_server *sv, Request *r, bool canceled)
             r->flow.assign(f, f + r->S);
         }
     }
-    sv->alloc.release(r->region_off, r->bytes);
+    {
+        std::lock_guard<std::mutex> la(sv->amu);
+        sv->alloc.release(r->region_off, r->bytes);
+    }
+    sv->acv.notify_all();
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->halloc.release(r->host_off, r->host_bytes);
     sv->slot_owner[q][slot] = nullptr;
@@ -621,6 +834,10 @@ static void server_loop(mf_server *sv)
                 }
                 r->state = COMPLETE;
                 r->t_done = Clock::now();
+            }
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                std::lock_guard<std::mutex> la(sv->amu);
                 sv->bytes_in_use = sv->alloc.used();
             }
             sv->cv.notify_all();
@@ -655,7 +872,10 @@ static void server_loop(mf_server *sv)
             }
             r->state = PUBLISHED;
             sv->st.admitted++;
-            sv->bytes_in_use = sv->alloc.used();
+            {
+                std::lock_guard<std::mutex> la(sv->amu);
+                sv->bytes_in_use = sv->alloc.used();
+            }
             sv->st.peak_bytes = std::max<size_t>(sv->st.peak_bytes, sv->bytes_in_use);
             progress = true;
         }
@@ -675,5 +895,254 @@ static void server_loop(mf_server *sv)
             else
                 sv->cv.wait_for(lk, std::chrono::microseconds(50));
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid lane worker: requests above the routing size, registrations and
+// re-solves of resident graphs, one at a time on the lane's own context.
+
+// Carves `bytes` of the region, waiting while the other lane holds the
+// space; false if the server is stopping.
+static bool carve(mf_server *sv, size_t bytes, size_t &off)
+{
+    std::unique_lock<std::mutex> la(sv->amu);
+    while (!sv->alloc.alloc(bytes, off)) {
+        if (sv->stop) return false;
+        sv->acv.wait_for(la, std::chrono::milliseconds(1));
+    }
+    return true;
+}
+
+static void uncarve(mf_server *sv, size_t off, size_t bytes)
+{
+    {
+        std::lock_guard<std::mutex> la(sv->amu);
+        sv->alloc.release(off, bytes);
+    }
+    sv->acv.notify_all();
+}
+
+static void fill_result(mf_result &R, mf_status st, const mf_stats &ss, double ms_start, double ms_end)
+{
+    R.status = st;
+    R.lanes_per_vertex = 0;
+    R.value = ss.value;
+    R.cut_capacity = ss.cut_capacity;
+    R.rounds = ss.rounds;
+    R.rounds2 = ss.rounds2;
+    R.global_relabels = ss.global_relabels;
+    R.global_relabels2 = ss.global_relabels2;
+    R.bfs_levels = ss.bfs_levels;
+    R.pushes = ss.pushes;
+    R.relabels = ss.relabels;
+    R.ms_start = ms_start;
+    R.ms_end = ms_end;
+}
+
+// Reads the sink side and the flow of a finished solve into the request.
+static mf_status take_device_outputs(mf_context *g, Request *r, const uint8_t *side_dev, const int32_t *flow_dev)
+{
+    r->side.resize((size_t)r->n);
+    hipError_t he = hipMemcpyAsync(r->side.data(), side_dev, (size_t)r->n, hipMemcpyDeviceToHost, g->stream);
+    if (he == hipSuccess && r->want_flow && r->S) {
+        r->flow.resize((size_t)r->S);
+        he = hipMemcpyAsync(r->flow.data(), flow_dev, 4 * (size_t)r->S, hipMemcpyDeviceToHost, g->stream);
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(g->stream);
+    return he == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
+static void grid_solve(mf_server *sv, Request *r)
+{
+    mf_context *g = sv->gctx;
+    const auto t0 = Clock::now();
+    const GridSlice G = grid_slice(r->n, r->S, r->want_flow, false);
+    size_t off;
+    if (!carve(sv, G.end, off)) {
+        r->result.status = MF_ECANCELED;
+        return;
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->st.admitted++;
+        std::lock_guard<std::mutex> la(sv->amu);
+        sv->bytes_in_use = sv->alloc.used();
+        sv->st.peak_bytes = std::max<size_t>(sv->st.peak_bytes, sv->bytes_in_use);
+    }
+    uint8_t *base = sv->region + off;
+    mf_graph mg{r->n, r->S, r->off.data(), r->head.data(), r->rev.data(), r->cap.data(), r->s, r->t};
+    mf_dgraph dg;
+    mf_stats ss;
+    memset(&ss, 0, sizeof ss);
+    mf_status st = upload_graph_into(g, &mg, base, G.lay, (int64_t *)(base + G.stage), &dg);
+    const double ms_in = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    if (st == MF_OK) {
+        Workspace w = workspace_in(base, G.lay, r->n, r->S);
+        mf_options o = r->opt;
+        o.flags &= ~(uint32_t)(MF_PROFILE | MF_WARM_START | MF_PERSISTENT);
+        int64_t val = 0;
+        st = solve_in_workspace(g, &dg, &o, &val, r->want_flow ? (int32_t *)(base + G.lay.flow) : nullptr,
+                                base + G.lay.side, &ss, &w, false);
+        if (st == MF_OK) st = take_device_outputs(g, r, base + G.lay.side, (int32_t *)(base + G.lay.flow));
+    }
+    fill_result(r->result, st, ss, ms_in, std::chrono::duration<double, std::milli>(Clock::now() - t0).count());
+    uncarve(sv, off, G.end);
+}
+
+static void grid_register(mf_server *sv, Request *r, Resident *res)
+{
+    mf_context *g = sv->gctx;
+    const GridSlice G = grid_slice(r->n, r->S, true, true);
+    size_t off;
+    if (!carve(sv, G.end, off)) {
+        r->result.status = MF_ECANCELED;
+        return;
+    }
+    res->off = off;
+    res->bytes = G.end;
+    res->lay = G.lay;
+    res->keep = G.keep;
+    uint8_t *base = sv->region + off;
+    mf_graph mg{r->n, r->S, r->off.data(), r->head.data(), r->rev.data(), r->cap.data(), r->s, r->t};
+    mf_dgraph dg;
+    mf_status st = upload_graph_into(g, &mg, base, G.lay, (int64_t *)(base + G.stage), &dg);
+    if (st != MF_OK) {
+        uncarve(sv, off, G.end);
+        res->bytes = 0;
+    } else {
+        res->valid = true;
+        res->maxdeg_inner = dg.maxdeg_inner;
+        res->deg_s = dg.deg_s;
+        res->deg_t = dg.deg_t;
+    }
+    r->result.status = st;
+}
+
+static void grid_resolve(mf_server *sv, Request *r, Resident *res)
+{
+    mf_context *g = sv->gctx;
+    const auto t0 = Clock::now();
+    mf_stats ss;
+    memset(&ss, 0, sizeof ss);
+    if (!res->valid) {
+        r->result.status = MF_EINVAL;
+        return;
+    }
+    uint8_t *base = sv->region + res->off;
+    const InstLayout &L = res->lay;
+    mf_dgraph dg;
+    dg.n = res->n;
+    dg.s = res->s;
+    dg.t = res->t;
+    dg.slots = res->S;
+    dg.off = (int32_t *)(base + L.off);
+    dg.head = (int32_t *)(base + L.head);
+    dg.rev = (int32_t *)(base + L.rev);
+    dg.cap = (int32_t *)(base + L.cap);
+    dg.maxdeg_inner = res->maxdeg_inner;
+    dg.deg_s = res->deg_s;
+    dg.deg_t = res->deg_t;
+    int32_t *keep = (int32_t *)(base + res->keep);
+    bool resumable = false;
+    mf_status st = check_caps_into(g, &dg, r->cap.data(), (int32_t *)(base + L.flow), keep, res->has_flow,
+                                   &resumable);
+    const double ms_in = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    if (st == MF_OK) {
+        Workspace w = workspace_in(base, L, res->n, res->S);
+        if (resumable) {
+            // the kept flow goes back into the workspace, e(t) its value
+            hipError_t he = hipSuccess;
+            if (res->S) he = hipMemcpyAsync(w.res, keep, 4 * (size_t)res->S, hipMemcpyDeviceToDevice, g->stream);
+            if (he == hipSuccess)
+                he = hipMemcpyAsync(w.e + res->t, &res->value, sizeof(int64_t), hipMemcpyHostToDevice, g->stream);
+            if (he == hipSuccess) he = hipStreamSynchronize(g->stream);
+            if (he != hipSuccess) st = MF_EDEVICE;
+        }
+        mf_options o = r->opt;
+        o.flags &= ~(uint32_t)(MF_PROFILE | MF_WARM_START | MF_PERSISTENT | MF_PREFLOW_ONLY);
+        int64_t val = 0;
+        if (st == MF_OK)
+            st = solve_in_workspace(g, &dg, &o, &val, (int32_t *)(base + L.flow), base + L.side, &ss, &w,
+                                    resumable);
+        if (st == MF_OK) {
+            // keep this flow for the next re-solve
+            hipError_t he = hipSuccess;
+            if (res->S) he = hipMemcpyAsync(keep, w.res, 4 * (size_t)res->S, hipMemcpyDeviceToDevice, g->stream);
+            if (he == hipSuccess) he = hipStreamSynchronize(g->stream);
+            if (he != hipSuccess) st = MF_EDEVICE;
+            res->has_flow = st == MF_OK;
+            res->value = val;
+        } else {
+            res->has_flow = false;
+        }
+        if (st == MF_OK) st = take_device_outputs(g, r, base + L.side, (int32_t *)(base + L.flow));
+    }
+    fill_result(r->result, st, ss, ms_in, std::chrono::duration<double, std::milli>(Clock::now() - t0).count());
+    r->result.resumed = resumable ? 1 : 0;
+}
+
+static void grid_loop(mf_server *sv)
+{
+    (void)hipSetDevice(sv->ctx->device);
+    while (!sv->stop) {
+        Request *r = nullptr;
+        Resident *res = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            // free released resident graphs that no queued request names
+            for (auto it = sv->residents.begin(); it != sv->residents.end();) {
+                Resident *x = it->second;
+                if (x->released && x->pending == 0) {
+                    if (x->bytes) uncarve(sv, x->off, x->bytes);
+                    delete x;
+                    it = sv->residents.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            if (sv->gpending.empty()) {
+                sv->cv.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+            r = sv->gpending.front();
+            sv->gpending.pop_front();
+            r->state = ADMITTING;
+            if (r->kind != SOLVE) {
+                auto it = sv->residents.find(r->graph_id);
+                res = it == sv->residents.end() ? nullptr : it->second;
+            }
+            sv->grid_busy = 1;
+        }
+        if (r->kind == SOLVE)
+            grid_solve(sv, r);
+        else if (!res)
+            r->result.status = MF_ENOTFOUND;
+        else if (r->kind == REGISTER)
+            grid_register(sv, r, res);
+        else
+            grid_resolve(sv, r, res);
+        std::vector<int64_t>().swap(r->off);
+        std::vector<int64_t>().swap(r->rev);
+        std::vector<int32_t>().swap(r->head);
+        std::vector<int32_t>().swap(r->cap);
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (res) res->pending--;
+            sv->grid_busy = 0;
+            if (r->kind != REGISTER) {
+                if (r->canceled) {
+                    r->result.status = MF_ECANCELED;
+                    sv->st.canceled++;
+                } else {
+                    sv->st.completed++;
+                }
+            }
+            r->state = COMPLETE;
+            r->t_done = Clock::now();
+            std::lock_guard<std::mutex> la(sv->amu);
+            sv->bytes_in_use = sv->alloc.used();
+        }
+        sv->cv.notify_all();
     }
 }

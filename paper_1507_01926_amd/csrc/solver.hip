@@ -216,7 +216,7 @@ void mf_context_destroy(mf_context *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     Workspace &w = ctx->ws;
     void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.touched,
-                    w.A, w.A2, w.C, w.Q, w.Q2, w.H};
+                    w.A, w.A2, w.C, w.Q, w.Q2, w.H, w.hr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
@@ -489,7 +489,7 @@ static mf_status ensure_workspace(mf_context *ctx, int64_t n, int64_t slots)
     if (w.n_cap >= n && w.s_cap >= slots && w.res) return MF_OK;
     // release the old one
     void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.touched,
-                    w.A, w.A2, w.C, w.Q, w.Q2, w.H};
+                    w.A, w.A2, w.C, w.Q, w.Q2, w.H, w.hr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     ctx->used -= std::min(ctx->used, w.bytes);
@@ -512,6 +512,7 @@ static mf_status ensure_workspace(mf_context *ctx, int64_t n, int64_t slots)
     if ((st = dalloc(ctx, (void **)&w.Q2, 4 * N)) != MF_OK) return st;
     if ((st = dalloc(ctx, (void **)&w.H, 4 * N)) != MF_OK) return st;
     if ((st = dalloc(ctx, (void **)&w.touched, N)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.hr, 4 * S)) != MF_OK) return st;
     w.n_cap = N;
     w.s_cap = S;
     w.bytes = ctx->used - before;
@@ -720,7 +721,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
 {
     mf_context *ctx = S.ctx;
     const int n = S.g.n;
-    launch_gr_init(S.g, S.st, sink, grid_for(n, 256, S.maxgrid), ctx->stream);
+    launch_gr_init(S.g, S.st, sink, grid_for(std::max<int64_t>(n, S.g.slots), 256, S.maxgrid), ctx->stream);
     int64_t nq = 1;
     int64_t unvisited = n - 2;
     std::vector<int> bu_lv;            // profiling: levels run bottom-up
@@ -1299,7 +1300,8 @@ static mf_status solve_small(mf_context *ctx, mf_dgraph *dg, const mf_options &o
 }
 
 static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt, int64_t *value,
-                                int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *ext = nullptr);
+                                int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *ext = nullptr,
+                                bool resume = false);
 
 extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, mf_stream stream, const mf_options *opt,
                                        int64_t *value, int32_t *flow_dev, uint8_t *side_dev,
@@ -1314,11 +1316,16 @@ extern "C" mf_status mf_solve_uploaded(mf_context *ctx, mf_dgraph *dg, mf_stream
     return st == MF_OK ? so : st;
 }
 
-// ext: a workspace carved by the caller (the no-allocation entry point); then
-// nothing is allocated, the graph is always solved by the grid-wide kernels,
-// and the context's resumable state is left alone.
+// ext: a workspace carved by the caller (the no-allocation entry point, the
+// large instances of the batched and served forms); then nothing is
+// allocated, the graph is always solved by the grid-wide kernels, and the
+// context's resumable state is left alone.  resume (with ext): the
+// workspace holds the residuals of a complete flow of this graph and e(t)
+// its value (a resident graph of the server), and the solve continues from
+// that flow as MF_WARM_START does.
 static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options *opt, int64_t *value,
-                                int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *ext)
+                                int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *ext,
+                                bool resume)
 {
     if (!ctx || !dg) return fail(ctx, MF_EINVAL, "NULL context or graph");
     mf_options o;
@@ -1330,14 +1337,15 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
     if (st != MF_OK) return st;
     const bool preflow_only = (o.flags & MF_PREFLOW_ONLY) != 0;
     if (preflow_only && flow_dev) return fail(ctx, MF_EINVAL, "flow output requires phase 2");
+    if (resume) o.flags |= MF_WARM_START;
     const bool warm = (o.flags & MF_WARM_START) != 0;
-    if (warm && ctx->warm_dg != dg)
+    if (warm && !resume && ctx->warm_dg != dg)
         return fail(ctx, MF_EINVAL, "no resumable flow of this graph on this context (MF_WARM_START needs a "
                                     "complete solve of it as the context's last solve, and capacities that "
                                     "still hold its flow)");
     if ((o.flags & MF_CHECK_INVARIANTS) && (o.flags & MF_PERSISTENT))
         return fail(ctx, MF_EINVAL, "MF_CHECK_INVARIANTS runs the host-driven rounds: not with MF_PERSISTENT");
-    if (ext && (warm || (o.flags & MF_PROFILE)))
+    if (ext && ((warm && !resume) || (o.flags & MF_PROFILE)))
         return fail(ctx, MF_EINVAL, "MF_WARM_START and MF_PROFILE are not available without allocation");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     if (!ext) {
@@ -1368,6 +1376,7 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
     S.st.C = w.C;
     S.st.Q = w.Q;
     S.st.Q2 = w.Q2;
+    S.st.hr = w.hr;
     S.st.ctl = ctx->ctl;
     S.opt = o;
     {
@@ -1554,6 +1563,82 @@ extern "C" mf_status mf_solve(mf_context *ctx, const mf_graph *host_g, const mf_
 }
 
 // ---------------------------------------------------------------------------
+// Pieces shared with the server's grid lane and the batched form's large
+// instances (declared in mf_host.h)
+
+mf_status solve_in_workspace(mf_context *ctx, mf_dgraph *dg, const mf_options *opt, int64_t *value,
+                             int32_t *flow_dev, uint8_t *side_dev, mf_stats *stats, Workspace *w, bool resume)
+{
+    return solve_uploaded(ctx, dg, opt, value, flow_dev, side_dev, stats, w, resume);
+}
+
+mf_status upload_graph_into(mf_context *ctx, const mf_graph *g, uint8_t *base, const InstLayout &L,
+                            int64_t *stage64, mf_dgraph *dg)
+{
+    const size_t S = (size_t)g->slots, N = (size_t)g->n;
+    dg->n = g->n;
+    dg->s = g->s;
+    dg->t = g->t;
+    dg->slots = g->slots;
+    dg->off = (int32_t *)(base + L.off);
+    dg->head = (int32_t *)(base + L.head);
+    dg->rev = (int32_t *)(base + L.rev);
+    dg->cap = (int32_t *)(base + L.cap);
+    int64_t *off64 = stage64, *rev64 = stage64 + (N + 1);
+    hipError_t he = hipMemcpyAsync(off64, g->offsets, 8 * (N + 1), hipMemcpyHostToDevice, ctx->stream);
+    if (he == hipSuccess && S) he = hipMemcpyAsync(rev64, g->rev, 8 * S, hipMemcpyHostToDevice, ctx->stream);
+    if (he == hipSuccess && S) he = hipMemcpyAsync(dg->head, g->head, 4 * S, hipMemcpyHostToDevice, ctx->stream);
+    if (he == hipSuccess && S) he = hipMemcpyAsync(dg->cap, g->cap, 4 * S, hipMemcpyHostToDevice, ctx->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream);
+    if (he != hipSuccess) return fail(ctx, MF_EDEVICE, "graph upload failed: %s", hipGetErrorString(he));
+    const int maxg = ctx->num_cus * 8;
+    launch_narrow(off64, rev64, dg->off, dg->rev, dg->n, dg->slots, ctx->ctl,
+                  grid_for(std::max<int64_t>(dg->slots, N + 1), 256, maxg), ctx->stream);
+    mf_status st = read_ctl(ctx);
+    if (st != MF_OK) return st;
+    if (ctx->ctl_host->err == 0) {
+        launch_validate(dg->view(), ctx->ctl, grid_for(S, 256, maxg), ctx->stream);
+        launch_degree_stats(dg->view(), ctx->ctl, grid_for(N, 256, maxg), ctx->stream);
+        if ((st = read_ctl(ctx)) != MF_OK) return st;
+    }
+    if (ctx->ctl_host->err) return fail(ctx, MF_EINVAL, "invalid graph: %s", validation_message(ctx->ctl_host->err));
+    dg->maxdeg_inner = ctx->ctl_host->maxdeg_inner;
+    dg->deg_s = ctx->ctl_host->deg_s;
+    dg->deg_t = ctx->ctl_host->deg_t;
+    return MF_OK;
+}
+
+// New capacities for a resident graph (host array): checked as at upload;
+// with has_flow the kept residuals move by the changes, and *resumable says
+// whether every new capacity still holds the kept flow.  MF_EINVAL leaves
+// the graph unchanged.  tmp_dev: int32[slots] device scratch.
+mf_status check_caps_into(mf_context *ctx, mf_dgraph *dg, const int32_t *cap_host, int32_t *tmp_dev,
+                          int32_t *keep_res, bool has_flow, bool *resumable)
+{
+    *resumable = false;
+    const int64_t S = dg->slots;
+    if (S == 0) {
+        *resumable = has_flow;
+        return MF_OK;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(tmp_dev, cap_host, 4 * S, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), ctx->stream));
+    const int maxg = ctx->num_cus * 8;
+    GraphView gv = dg->view();
+    gv.cap = tmp_dev;
+    launch_validate(gv, ctx->ctl, grid_for(S, 256, maxg), ctx->stream);
+    mf_status st = read_ctl(ctx);
+    if (st != MF_OK) return st;
+    if (ctx->ctl_host->err)
+        return fail(ctx, MF_EINVAL, "invalid capacities: %s", validation_message(ctx->ctl_host->err));
+    if (has_flow) launch_recap(dg->view(), tmp_dev, keep_res, 1, ctx->ctl, grid_for(S, 256, maxg), ctx->stream);
+    HIPCHK(ctx, hipMemcpyAsync(dg->cap, tmp_dev, 4 * S, hipMemcpyDeviceToDevice, ctx->stream));
+    if ((st = read_ctl(ctx)) != MF_OK) return st;
+    *resumable = has_flow && !(ctx->ctl_host->err & 128);
+    return MF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // The solve of mf_solve_device without device allocation
 
 // Byte offsets of the graph copies and the per-solve state inside the
@@ -1695,7 +1780,7 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
             results[i].status = MF_EINVAL;
             continue;
         }
-        lay[i] = layout_for(total, g.n, g.slots, flows && flows[i]);
+        lay[i] = layout_for(total, g.n, g.slots, flows && flows[i], g.slots > batch_grid_slots(o[i]));
         total = lay[i].end;
         max_n = std::max<int64_t>(max_n, g.n);
         max_S = std::max<int64_t>(max_S, g.slots);
@@ -1765,6 +1850,7 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
         // k_validate relies on valid offsets; it only reads segments inside [0, slots) because k_narrow
         // clamps bad offsets to 0, so run it and report either error.
         launch_validate(gv, c0, grid_for(S, 256, maxg), s0);
+        launch_degree_stats(gv, c0, grid_for(N, 256, maxg), s0);
         BatchItem &it = items[i];
         it.g = gv;
         StateView sv;
@@ -1812,11 +1898,16 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
     if (he == hipSuccess) he = hipStreamSynchronize(s0);
     if (he != hipSuccess) return dev_err(he, "validation read-back");
     std::vector<std::vector<int32_t>> bucket(4);
+    std::vector<int32_t> large;          // solved by the grid-wide kernels after the batch launch
     for (int i = 0; i < k; i++) {
         if (!ok[i]) continue;
         if (hc[5 * (size_t)i].err) {
             ok[i] = 0;
             results[i].status = MF_EINVAL;
+            continue;
+        }
+        if (graphs[i].slots > batch_grid_slots(o[i])) {
+            large.push_back(i);
             continue;
         }
         const int G = items[i].G;
@@ -1844,8 +1935,13 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
         release();
         return st;
     }
+    const auto t_launch = std::chrono::steady_clock::now();
+    float ms = 0;
+    std::vector<BatchResult> hr((size_t)k);
+    const bool any_small = !order.empty();
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    if (any_small) {
     he = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
     if (he != hipSuccess) return dev_err(he, "hipStreamBeginCapture");
     (void)hipEventRecord(ctx->bev[4], s0);
@@ -1876,16 +1972,68 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
     (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
     if (he != hipSuccess) return dev_err(he, "batch launch");
-    float ms = 0;
     (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]);
-    std::vector<BatchResult> hr((size_t)k);
     he = hipMemcpy(hr.data(), res_d, sizeof(BatchResult) * (size_t)k, hipMemcpyDeviceToHost);
     if (he != hipSuccess) return dev_err(he, "batch results");
+    }
+    // Instances above the routing size: one after another by the grid-wide
+    // kernels (a workgroup per instance would take seconds on the largest),
+    // each over its own slice of the arena.
+    std::vector<char> big((size_t)k, 0);
+    for (int i : large) {
+        big[i] = 1;
+        const mf_graph &gh = graphs[i];
+        const InstLayout &L = lay[i];
+        const Ctl &c0 = hc[5 * (size_t)i];
+        mf_dgraph dg;
+        dg.n = gh.n;
+        dg.s = gh.s;
+        dg.t = gh.t;
+        dg.slots = gh.slots;
+        dg.off = (int32_t *)(arena + L.off);
+        dg.head = (int32_t *)(arena + L.head);
+        dg.rev = (int32_t *)(arena + L.rev);
+        dg.cap = (int32_t *)(arena + L.cap);
+        dg.maxdeg_inner = c0.maxdeg_inner;
+        dg.deg_s = c0.deg_s;
+        dg.deg_t = c0.deg_t;
+        Workspace w = workspace_in(arena, L, gh.n, gh.slots);
+        mf_options oi = o[i];
+        oi.flags &= ~(uint32_t)MF_PROFILE;
+        mf_stats sst;
+        int64_t val = 0;
+        const double t_in = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_launch).count();
+        mf_status sr = solve_uploaded(ctx, &dg, &oi, &val, L.flow ? (int32_t *)(arena + L.flow) : nullptr,
+                                      arena + L.side, &sst, &w);
+        mf_result &R = results[i];
+        R.status = sr;
+        R.lanes_per_vertex = 0;
+        R.value = sst.value;
+        R.cut_capacity = sst.cut_capacity;
+        R.rounds = sst.rounds;
+        R.rounds2 = sst.rounds2;
+        R.global_relabels = sst.global_relabels;
+        R.global_relabels2 = sst.global_relabels2;
+        R.bfs_levels = sst.bfs_levels;
+        R.pushes = sst.pushes;
+        R.relabels = sst.relabels;
+        R.ms_start = t_in;
+        R.ms_end = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_launch).count();
+        if (sr == MF_EDEVICE) {
+            release();
+            return sr;
+        }
+        const size_t S = (size_t)gh.slots, N = (size_t)gh.n;
+        he = hipSuccess;
+        if (flows && flows[i] && S && (sr == MF_OK)) he = hipMemcpy(flows[i], arena + L.flow, 4 * S, hipMemcpyDeviceToHost);
+        if (he == hipSuccess && sides && sides[i]) he = hipMemcpy(sides[i], arena + L.side, N, hipMemcpyDeviceToHost);
+        if (he != hipSuccess) return dev_err(he, "batch output copy");
+    }
     int64_t t0 = INT64_MAX;
     for (int i = 0; i < k; i++)
-        if (ok[i]) t0 = std::min(t0, hr[i].t_start);
+        if (ok[i] && !big[i]) t0 = std::min(t0, hr[i].t_start);
     for (int i = 0; i < k; i++) {
-        if (!ok[i]) continue;
+        if (!ok[i] || big[i]) continue;
         const BatchResult &r = hr[i];
         mf_result &R = results[i];
         R.status = r.status == 0 ? MF_OK : r.status == 1 ? MF_ETIMEOUT : MF_EDEVICE;
@@ -1908,7 +2056,9 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
     }
     if (stats) {
         memset(stats, 0, sizeof *stats);
-        stats->ms_total = ms;
+        stats->ms_total = large.empty() ? ms
+                                        : std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                                  t_launch).count();
     }
     release();
     return MF_OK;
