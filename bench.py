@@ -7,14 +7,17 @@ reconstruction, value, per-slot flow and sink side), with the graph already
 resident in HBM (uploaded and validated before the timed region, as the
 paper excludes data-structure initialisation).
 
-Default workload: the 2048x2048 8-connected image-segmentation grid
-(4,194,306 vertices, 37,724,164 arcs).  Prints one JSON line.
+Default workload: the largest single-GPU configuration, the 256^3
+6-connected grid (16,777,218 vertices, 100,401,152 arcs).  Prints one JSON
+line.  The 2048x2048 segmentation grid is timed too and reported beside it.
 
 The global-relabel schedule (the relabel frequency of Sec. 3's work rule,
-a per-round and a per-level charge) is picked by the autotuner before the
-warm-up, from timed plain solves of the graph (a few candidate schedules);
---fixed-schedule uses the fixed rule instead.  The schedule never changes
-the value, the cut or the sink side.
+a per-round and a per-level charge) comes from the committed schedule cache
+(paper_1507_01926_amd/schedules.json), which the autotuner wrote from timed
+solves of ANOTHER instance of the same family and size; the fixed rule is
+timed beside it.  --schedule fixed uses the fixed rule, --schedule tune
+tunes on another instance first.  The schedule never changes the value, the
+cut or the sink side.
 """
 from __future__ import annotations
 
@@ -99,18 +102,30 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline_leg(g, workload: str) -> dict:
+# The CPU oracle's sample of each workload: the same generator rule at a
+# size whose sequential solve takes about 10-30 s (the full 256^3 grid takes
+# tens of minutes on one core).
+CPU_SAMPLE = {"c1": 1, "c2": 1, "c3": 3, "c4a": 4, "c4b": 1}
+
+
+def cpu_baseline_leg(workload: str) -> dict:
     """The CPU oracle (sequential FIFO push-relabel, exact int64, one thread)
-    timed on this host: one complete solve of the same instance."""
+    timed on this host: one complete solve (preflow and flow) of a bounded
+    sample of the workload, reported as arcs/s of that sample."""
     import oracle
+    from workloads import make_config
+    f = CPU_SAMPLE.get(workload, 1)
+    g = make_config(workload, f)
     t0 = time.perf_counter()
     A = oracle.fifo_maxflow(g)
     dt = time.perf_counter() - t0
+    what = "the full instance" if f == 1 else (f"the same generator rule with every side divided by {f} "
+                                               f"({g.n:,} vertices, {g.m_arcs:,} arcs)")
     return {"value": g.m_arcs / dt, "unit": "arcs/s", "cores": 1, "kind": "oracle",
-            "sample": f"one complete solve (preflow + flow) of the full {workload} instance, "
-                      f"sequential FIFO push-relabel with global relabels, 1 thread, "
-                      f"{dt:.1f} s; host CPU: {cpu_model()}, {os.cpu_count()} logical cores",
-            "seconds": dt, "oracle_value": A["value"]}
+            "sample": f"{workload}: one complete solve (preflow + flow) of {what}, sequential FIFO "
+                      f"push-relabel with global relabels, 1 thread, {dt:.1f} s; host CPU: {cpu_model()}, "
+                      f"{os.cpu_count()} logical cores",
+            "seconds": dt, "oracle_value": A["value"], "sample_arcs": g.m_arcs}
 
 
 def _pct(xs, q):
@@ -201,24 +216,83 @@ def stream_leg(count: int, n_hi: float, seed_note: str) -> dict:
             "plain_one_at_a_time_solves_per_s": count / sum(service)}
 
 
+def schedule_options(g, knobs: dict) -> dict:
+    thr = 12 * g.n + 2 * g.slots
+    return dict(gr_round_charge=max(1, thr // knobs["round_divisor"]) if knobs.get("round_divisor") else 0,
+                gr_freq_num=1, gr_freq_den=knobs.get("freq_den", 2), gr_level_charge=knobs.get("level_charge", 0))
+
+
+def pick_schedule(mode: str, workload: str, g, ctx, level_charge: int):
+    """(schedule options, where they came from)."""
+    fixed = fixed_schedule(g, level_charge)
+    if mode == "fixed":
+        return fixed, "fixed rule"
+    if mode == "paper":
+        return {}, "the paper's rule"
+    from paper_1507_01926_amd.autotune import cached_schedule, tune_workload_schedules
+    if mode == "tune":
+        print("[bench] autotuning the schedule on another instance of the family", file=sys.stderr, flush=True)
+        entry = tune_workload_schedules([workload], path=os.path.join(ROOT, "_tuned_schedules.json"))[workload]
+        return schedule_options(g, entry["knobs"]), "autotuner, " + entry["tuned_on"]
+    entry = cached_schedule(workload)
+    if entry is None:
+        return fixed, "fixed rule (no cached schedule for this workload)"
+    return schedule_options(g, entry["knobs"]), "schedule cache: autotuner on " + entry["tuned_on"]
+
+
+def time_solves(dg, g, opt, flow, side, steps: int, warmup: int, pick_dominant: bool, mf):
+    """Warm-up and timed solves of an uploaded graph; returns the timing and
+    the per-kernel tables."""
+    import torch
+
+    def per_kernel(rs):
+        out = {}
+        for i, name in enumerate(mf.KERNEL_NAMES):
+            out[name] = (sum(r["kernel_ms"][i] for r in rs), sum(r["kernel_bytes"][i] for r in rs),
+                         sum(r["kernel_launches"][i] for r in rs), sum(r["kernel_timed"][i] for r in rs))
+        return out
+
+    # Warm-up solves time every kernel with HIP events and name the dominant
+    # one; the timed solves then bracket only that kernel's launches, and of
+    # a kernel launched thousands of times per solve only every 16th launch
+    # (an event pair costs a few microseconds of device time).
+    warm = [dg.solve(opt, flow.data_ptr(), side.data_ptr()) for _ in range(warmup)]
+    torch.cuda.synchronize()
+    dom_idx = None
+    if warm and pick_dominant:
+        wk = per_kernel(warm[-1:])
+        dom_idx = mf.KERNEL_NAMES.index(max(wk, key=lambda k: wk[k][0]))
+        opt.profile_mask = 1 << dom_idx
+        opt.profile_stride = 16 if wk[mf.KERNEL_NAMES[dom_idx]][2] >= 256 else 1
+    t0 = time.perf_counter()
+    runs = [dg.solve(opt, flow.data_ptr(), side.data_ptr()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kernels = per_kernel(runs)
+    table = per_kernel(warm[-1:]) if warm and dom_idx is not None else kernels
+    return dict(dt=dt, runs=runs, kernels=kernels, table=table, dom_idx=dom_idx,
+                table_steps=1 if warm and dom_idx is not None else steps)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--extra", default="c2",
+                    help="comma-separated workloads timed beside the headline (5 solves each; '' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--persistent", action="store_true",
                     help="run each phase as one persistent cooperative kernel instead of one launch per round")
-    ap.add_argument("--paper-schedule", action="store_true",
-                    help="use the paper's global-relabel rule without the per-round charge")
+    ap.add_argument("--schedule", default="cache", choices=("cache", "fixed", "tune", "paper"),
+                    help="global-relabel schedule: the committed cache (tuned on another instance of the "
+                         "family), the fixed rule, a fresh tuning on another instance, or the paper's rule")
     ap.add_argument("--simple-rounds", action="store_true",
                     help="rounds of the simple synchronous variant of Sec. 3 (ablation of Listing 1's rounds)")
-    ap.add_argument("--fixed-schedule", action="store_true",
-                    help="use the fixed rule (paper's frequency plus a per-round charge of (12n+2m)/128, and "
-                         "--level-charge) instead of the schedule the autotuner picks for this graph")
+    ap.add_argument("--gap", action="store_true", help="the gap rule at every round end (ablation)")
     ap.add_argument("--level-charge", type=int, default=0,
-                    help="global-relabel threshold charge per level of the last relabel's search")
+                    help="with --schedule fixed: global-relabel threshold charge per level of the last search")
     ap.add_argument("--stream", type=int, default=256,
                     help="instances of the batched/served stream leg (0 = skip)")
     ap.add_argument("--stream-nmax", type=float, default=1e5)
@@ -237,75 +311,54 @@ def main():
 
     print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
     g = make_config(args.workload)
-    sched = {} if args.paper_schedule else fixed_schedule(g, args.level_charge)
     ctx = mf.Context(0)
     dg = ctx.upload(g)                       # residency + validation: not timed
     dev = torch.device("cuda:0")
     flow = torch.empty(max(1, g.slots), dtype=torch.int32, device=dev)
     side = torch.empty(g.n, dtype=torch.uint8, device=dev)
-    tuned = None
-    if not (args.fixed_schedule or args.paper_schedule):
-        from paper_1507_01926_amd.autotune import Autotuner
-        print("[bench] autotuning the global-relabel schedule", file=sys.stderr, flush=True)
-        tuned = Autotuner(ctx, cache_path=None).tune_schedule(dg, g, reps=2, verbose=True)
-        k = tuned["knobs"]
-        thr = 12 * g.n + 2 * g.slots
-        sched = dict(gr_round_charge=max(1, thr // k["round_divisor"]), gr_freq_num=1,
-                     gr_freq_den=k["freq_den"], gr_level_charge=k["level_charge"])
-    opt = mf.options(profile=True, persistent=args.persistent, simple_rounds=args.simple_rounds, **sched)
+    sched, sched_from = pick_schedule(args.schedule, args.workload, g, ctx, args.level_charge)
+    mode = dict(simple_rounds=args.simple_rounds)
+    if args.gap:
+        mode["gap"] = True
+    opt = mf.options(profile=True, persistent=args.persistent, **mode, **sched)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    def per_kernel(rs):
-        out = {}
-        for i, name in enumerate(mf.KERNEL_NAMES):
-            out[name] = (sum(r["kernel_ms"][i] for r in rs), sum(r["kernel_bytes"][i] for r in rs),
-                         sum(r["kernel_launches"][i] for r in rs), sum(r["kernel_timed"][i] for r in rs))
-        return out
-
-    # Warm-up solves time every kernel with HIP events and name the dominant
-    # one; the timed solves then bracket only that kernel's launches, and of
-    # a kernel launched thousands of times per solve only every 16th launch
-    # (an event pair costs a few microseconds of device time).
-    print(f"[bench] warmup x{args.warmup}", file=sys.stderr, flush=True)
-    warm = [dg.solve(opt, flow.data_ptr(), side.data_ptr()) for _ in range(args.warmup)]
-    torch.cuda.synchronize()
-    dom_idx = None
-    if warm and not args.persistent:
-        wk = per_kernel(warm[-1:])
-        dom_idx = mf.KERNEL_NAMES.index(max(wk, key=lambda k: wk[k][0]))
-        opt.profile_mask = 1 << dom_idx
-        opt.profile_stride = 16 if wk[mf.KERNEL_NAMES[dom_idx]][2] >= 256 else 1
-    print(f"[bench] timing x{args.steps}", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    runs = []
-    for _ in range(args.steps):
-        runs.append(dg.solve(opt, flow.data_ptr(), side.data_ptr()))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    print(f"[bench] warmup x{args.warmup}, timing x{args.steps}", file=sys.stderr, flush=True)
+    T = time_solves(dg, g, opt, flow, side, args.steps, args.warmup, not args.persistent, mf)
+    dt, runs, kernels, table = T["dt"], T["runs"], T["kernels"], T["table"]
     ms_per_step = 1e3 * dt / args.steps
     value = g.m_arcs * args.steps / dt
 
     # dominant kernel over the timed region, from the library's HIP events
     # (recorded around each launch on the stream the kernels run on)
     tot = {k: sum(r[k] for r in runs) for k in runs[0] if isinstance(runs[0][k], (int, float))}
-    kernels = per_kernel(runs)
-    table = per_kernel(warm[-1:]) if warm and dom_idx is not None else kernels
-    table_steps = 1 if warm and dom_idx is not None else args.steps
+    table_steps = T["table_steps"]
     if args.persistent:
-        # one cooperative kernel per phase does all the work of the rounds
         kernels = {"k_phase": (tot["ms_phase_kernel"], tot["discharge_bytes"] + tot["merge_bytes"]
                                + tot["global_relabel_bytes"], tot["phase_launches"], tot["phase_launches"])}
         table, table_steps = kernels, args.steps
-    dom = mf.KERNEL_NAMES[dom_idx] if dom_idx is not None else max(kernels, key=lambda k: kernels[k][0])
+    dom = mf.KERNEL_NAMES[T["dom_idx"]] if T["dom_idx"] is not None else max(kernels, key=lambda k: kernels[k][0])
     ms_k, bytes_k, launches_k, timed_k = kernels[dom]
     avg_launch_ms = ms_k / max(1, timed_k)
     achieved = bytes_k / max(1, launches_k) / (avg_launch_ms * 1e-3) / 1e9 if ms_k > 0 else 0.0
     alg_bytes_total = tot["discharge_bytes"] + tot["merge_bytes"] + tot["global_relabel_bytes"]
     r0 = runs[0]
+    fixed = None
+    if args.schedule != "fixed" and not args.persistent:
+        # the fixed rule beside the tuned schedule (one solve)
+        fopt = mf.options(persistent=False, **mode, **fixed_schedule(g, 0))
+        t1 = time.perf_counter()
+        fr = dg.solve(fopt, flow.data_ptr(), side.data_ptr())
+        torch.cuda.synchronize()
+        fdt = time.perf_counter() - t1
+        assert fr["value"] == r0["value"]
+        fixed = {"ms_per_solve": 1e3 * fdt, "arcs_per_s": g.m_arcs / fdt, "solves": 1,
+                 "schedule": fixed_schedule(g, 0), "rounds": fr["rounds"], "rounds_phase2": fr["rounds2"],
+                 "global_relabels": fr["global_relabels"] + fr["global_relabels2"]}
     line = {
         "metric": METRIC,
         "value": value,
@@ -322,9 +375,10 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "n": g.n, "arcs": g.m_arcs, "slots": g.slots,
                    "schedule": sched or "paper (freq 1/2, alpha 6, beta 12)",
-                   "schedule_from": "autotuner (timed plain solves of this graph)" if tuned else "fixed rule",
+                   "schedule_from": sched_from,
                    "rounds": "simple synchronous variant (Sec. 3)" if args.simple_rounds
-                             else "Listing 1 (win criterion, full discharge)"},
+                             else "Listing 1 (win criterion, full discharge)",
+                   "gap_rule": bool(args.gap)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, args.workload),
@@ -347,14 +401,36 @@ def main():
                                            if table is not kernels else "event-timed in the timed solves",
                   "alg_GBps_whole_solve": alg_bytes_total / dt / 1e9,
                   "alg_frac_whole_solve": alg_bytes_total / dt / 1e9 / HBM_PEAK_GBS},
+        "fixed_schedule": fixed,
     }
+    dg.free()
+    del flow, side
+    extra = {}
+    for name in [x for x in args.extra.split(",") if x and x != args.workload]:
+        print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
+        ge = make_config(name)
+        dge = ctx.upload(ge)
+        fe = torch.empty(max(1, ge.slots), dtype=torch.int32, device=dev)
+        se = torch.empty(ge.n, dtype=torch.uint8, device=dev)
+        sc_e, from_e = pick_schedule("cache" if args.schedule in ("cache", "tune") else args.schedule, name, ge, ctx, 0)
+        Te = time_solves(dge, ge, mf.options(**mode, **sc_e), fe, se, 5, 1, False, mf)
+        re0 = Te["runs"][0]
+        extra[name] = {"workload": WORKLOADS[name], "arcs": ge.m_arcs, "arcs_per_s": ge.m_arcs * 5 / Te["dt"],
+                       "ms_per_solve": 1e3 * Te["dt"] / 5, "solves": 5, "value": re0["value"],
+                       "value_equals_cut": re0["value"] == re0["cut_capacity"], "schedule": sc_e,
+                       "schedule_from": from_e, "rounds": re0["rounds"], "rounds_phase2": re0["rounds2"],
+                       "ms_preflow": re0["ms_preflow"]}
+        dge.free()
+        del fe, se
+    if extra:
+        line["extra"] = extra
     ctx.close()
     if args.stream > 0:
         print(f"[bench] stream leg x{args.stream}", file=sys.stderr, flush=True)
         line["stream"] = stream_leg(args.stream, args.stream_nmax, "seeded")
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline_leg(g, args.workload)
+        line["cpu_baseline"] = cpu_baseline_leg(args.workload)
     print(json.dumps(line), flush=True)
 
 

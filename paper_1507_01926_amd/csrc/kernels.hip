@@ -512,14 +512,23 @@ __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView s
     const int groups = blockDim.x / G;
     if (blockIdx.x * groups >= na) return;          // no vertex for this block
     DisAcc acc;
-    for (int i = blockIdx.x * groups + threadIdx.x / G; i < na; i += gridDim.x * groups) {
+    MF_STAGE(stage);
+    stage_init(stage);
+    // every wave of the block runs the same number of iterations (the
+    // vertices past na do nothing), so the stage's barriers see every wave
+    const int span = gridDim.x * groups;
+    const int iters = (na - blockIdx.x * groups + span - 1) / span;
+    int i = blockIdx.x * groups + threadIdx.x / G;
+    for (int it = 0; it < iters; it++, i += span) {
+        if (i >= na) continue;
         const int v = st.A[i];
         if (g.off[v + 1] - g.off[v] > p.hubd) {        // left to k_discharge_hubs
             wave_append(gl == 0, v, st.H, &st.ctl->nhd);
             continue;
         }
-        discharge_vertex<G, false>(g, st, p, v, gl, acc);
+        discharge_vertex<G, false>(g, st, p, v, gl, acc, &stage);
     }
+    stage_flush_owner(stage, st.C, &st.ctl->nc, st.owner);
     discharge_flush(st, p, acc);
 }
 

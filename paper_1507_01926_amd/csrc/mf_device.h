@@ -240,6 +240,54 @@ __device__ __forceinline__ void stage_flush(Stage &sg, int32_t *list, int32_t *c
     for (int j = threadIdx.x; j < total; j += blockDim.x) list[g0 + j] = sg.buf[j];
 }
 
+// As stage_append for the candidate list of a list round, whose entries
+// carry their own index in owner[] (owner[w] = the entry that merges w).
+// Entries that overflow the LDS buffer get their index at once; the others
+// when the block flushes (stage_flush_owner).
+__device__ __forceinline__ void stage_append_owner(Stage &sg, bool pred, int32_t val, int32_t *list,
+                                                   int32_t *count, int32_t *owner)
+{
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const int c = __popcll(mask);
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int pos = 0;
+    if (lane_id() == leader) pos = atomicAdd(sg.cnt, c);
+    pos = __shfl(pos, leader);
+    const int first_over = pos > STAGE_CAP ? pos : STAGE_CAP;
+    const int n_over = pos + c - first_over;
+    int g0 = 0;
+    if (n_over > 0) {
+        if (lane_id() == leader) g0 = atomicAdd(count, n_over);
+        g0 = __shfl(g0, leader);
+    }
+    if (pred) {
+        const int idx = pos + lanes_below(mask);
+        if (idx < STAGE_CAP) {
+            sg.buf[idx] = val;
+        } else {
+            const int at = g0 + idx - first_over;
+            list[at] = val;
+            owner[val] = at;
+        }
+    }
+}
+
+// Must be reached by every thread of the block.
+__device__ __forceinline__ void stage_flush_owner(Stage &sg, int32_t *list, int32_t *count, int32_t *owner)
+{
+    __syncthreads();
+    const int total = *sg.cnt < STAGE_CAP ? *sg.cnt : STAGE_CAP;
+    if (threadIdx.x == 0) *sg.base = total ? atomicAdd(count, total) : 0;
+    __syncthreads();
+    const int g0 = *sg.base;
+    for (int j = threadIdx.x; j < total; j += blockDim.x) {
+        const int w = sg.buf[j];
+        list[g0 + j] = w;
+        owner[w] = g0 + j;
+    }
+}
+
 #define MF_STAGE(name)                           \
     __shared__ int32_t name##_buf[STAGE_CAP];    \
     __shared__ int32_t name##_cnt, name##_base;  \

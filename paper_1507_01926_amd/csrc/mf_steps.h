@@ -14,11 +14,14 @@ namespace mf {
 // The sink never discharges and nobody reads its own slots or its excess
 // during a round, so a push into the sink updates the reverse slot directly
 // (each slot has one pusher) and is added to the sink's excess once per block.
+// sg (list rounds of the grid-wide kernels): the candidate appends collect
+// in the block's LDS stage (one global atomic per block); null: one atomic
+// per wave.
 template <int G, bool DENSE>
 __device__ __forceinline__ int chunk_pass(const GraphView &g, StateView &st, int v, int dv, int dp,
                                           int gl, int a, int &r, int w, int dw, bool aw,
                                           int64_t &el, bool &lose, int64_t &pushes, int sink,
-                                          int64_t &to_sink, bool simple)
+                                          int64_t &to_sink, bool simple, Stage *sg)
 {
     const bool adm = r > 0 && dp == dw + 1;
     const bool win = (dv == dw + 1) || (dv < dw - 1) || (dv == dw && v < w);
@@ -47,8 +50,12 @@ __device__ __forceinline__ int chunk_pass(const GraphView &g, StateView &st, int
     }
     if (!DENSE) {
         const bool app = dl > 0 && !into_sink;
-        const int idx = wave_append(app, w, st.C, &st.ctl->nc);
-        if (app) st.owner[w] = idx;
+        if (sg) {
+            stage_append_owner(*sg, app, w, st.C, &st.ctl->nc, st.owner);
+        } else {
+            const int idx = wave_append(app, w, st.C, &st.ctl->nc);
+            if (app) st.owner[w] = idx;
+        }
     }
     el = tot >= el ? 0 : el - tot;
     return dl;
@@ -62,7 +69,7 @@ struct DisAcc {
 // Listing 1 for one element of the working set).
 template <int G, bool DENSE>
 __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &st, const RoundParams &p,
-                                                 int v, int gl, DisAcc &acc)
+                                                 int v, int gl, DisAcc &acc, Stage *sg = nullptr)
 {
     const int n = g.n;
     const int beg = g.off[v], end = g.off[v + 1], deg = end - beg;
@@ -91,7 +98,7 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
             if (gl == 0) acc.scans += deg;
             bool lose;
             if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, acc.pushes, p.sink,
-                                     acc.to_sink, p.simple) > 0)
+                                     acc.to_sink, p.simple, sg) > 0)
                 dirty = true;
             if (el == 0) break;
             const int cand = (r > 0 && dw >= dp) ? dw + 1 : n;
@@ -125,7 +132,7 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
                 if (gl == 0) acc.scans += (end - base) < G ? (end - base) : G;
                 bool lose;
                 if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a, r, w, dw, aw, el, lose, acc.pushes, p.sink,
-                                         acc.to_sink, p.simple) > 0)
+                                         acc.to_sink, p.simple, sg) > 0)
                     st.res[a] = r;
                 if (el == 0) break;
                 if (r > 0 && dw >= dp && dw + 1 < cand) cand = dw + 1;
@@ -149,8 +156,12 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
         if (DENSE) st.touched[v] = 1;
     }
     if (!DENSE) {
-        const int idx = wave_append(gl == 0, v, st.C, &st.ctl->nc);
-        if (gl == 0) st.owner[v] = idx;
+        if (sg) {
+            stage_append_owner(*sg, gl == 0, v, st.C, &st.ctl->nc, st.owner);
+        } else {
+            const int idx = wave_append(gl == 0, v, st.C, &st.ctl->nc);
+            if (gl == 0) st.owner[v] = idx;
+        }
     }
 }
 

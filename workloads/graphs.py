@@ -368,15 +368,17 @@ CONFIGS = {
 }
 
 
-def make_config(name: str, scale_down: int = 1) -> Graph:
+def make_config(name: str, scale_down: int = 1, seed_offset: int = 0) -> Graph:
     """Instance of a named configuration.
 
     ``scale_down`` shrinks every linear dimension by that factor (same
     generator, same seed) for tests that need the same family at a size the
-    oracle finishes quickly.
+    oracle finishes quickly.  ``seed_offset`` draws another instance of the
+    same family and size (the schedule autotuner tunes on one of those, not on
+    the instance the benchmark times).
     """
     k = {"c1": 0, "c2": 1, "c3": 2, "c4a": 3, "c4b": 3}[name]
-    seed = SEED_BASE + k + (100 if name == "c4b" else 0)
+    seed = SEED_BASE + k + (100 if name == "c4b" else 0) + int(seed_offset)
     f = int(scale_down)
     if name == "c1":
         return grid2d4(max(2, 64 // f), max(2, 64 // f), seed)
