@@ -105,7 +105,7 @@ def cpu_model() -> str:
 # The CPU oracle's sample of each workload: the same generator rule at a
 # size whose sequential solve takes about 10-30 s (the full 256^3 grid takes
 # tens of minutes on one core).
-CPU_SAMPLE = {"c1": 1, "c2": 1, "c3": 3, "c4a": 4, "c4b": 1}
+CPU_SAMPLE = {"c1": 1, "c2": 1, "c3": 2, "c4a": 4, "c4b": 1}
 
 
 def cpu_baseline_leg(workload: str) -> dict:
@@ -291,6 +291,7 @@ def main():
     ap.add_argument("--simple-rounds", action="store_true",
                     help="rounds of the simple synchronous variant of Sec. 3 (ablation of Listing 1's rounds)")
     ap.add_argument("--gap", action="store_true", help="the gap rule at every round end (ablation)")
+    ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-rule solve beside the tuned schedule")
     ap.add_argument("--level-charge", type=int, default=0,
                     help="with --schedule fixed: global-relabel threshold charge per level of the last search")
     ap.add_argument("--stream", type=int, default=256,
@@ -348,7 +349,7 @@ def main():
     alg_bytes_total = tot["discharge_bytes"] + tot["merge_bytes"] + tot["global_relabel_bytes"]
     r0 = runs[0]
     fixed = None
-    if args.schedule != "fixed" and not args.persistent:
+    if args.schedule != "fixed" and not args.persistent and not args.no_fixed:
         # the fixed rule beside the tuned schedule (one solve)
         fopt = mf.options(persistent=False, **mode, **fixed_schedule(g, 0))
         t1 = time.perf_counter()

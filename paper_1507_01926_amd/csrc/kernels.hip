@@ -613,9 +613,25 @@ __global__ __launch_bounds__(256) void k_merge_dense(GraphView g, StateView st, 
 }
 
 // Lists the vertices whose flag is set (in any order) and adds their number
-// to *count.  Each lane tests 16 flags with one 16-byte load; a block scan
-// places the entries and one atomic per block reserves their range.
+// to *count.  Each lane tests 16 flags with one 16-byte load per step; a
+// block scan places the step's entries in an LDS buffer that collects the
+// block's entries over all its steps, and the block writes the buffer out
+// with one atomic on *count when it is full or the block is done (device
+// atomics on one counter serialize, so a launch makes as few as it can).
 // flags must be 16-byte aligned.
+constexpr int COMPACT_CAP = 8192;     // entries; a step adds at most 256 * 16 = 4096
+
+__device__ __forceinline__ void compact_flush(int32_t *list, int32_t *count, int32_t *buf, int &held, int *s_base)
+{
+    // all threads of the block, held is block-uniform
+    if (threadIdx.x == 0) *s_base = held ? atomicAdd(count, held) : 0;
+    __syncthreads();
+    const int g0 = *s_base;
+    for (int j = threadIdx.x; j < held; j += blockDim.x) list[g0 + j] = buf[j];
+    __syncthreads();
+    held = 0;
+}
+
 __global__ __launch_bounds__(256) void k_compact_flags(const uint8_t *__restrict__ flags, int n,
                                                       int32_t *__restrict__ list, int32_t *count,
                                                       const int32_t *stop)
@@ -623,8 +639,10 @@ __global__ __launch_bounds__(256) void k_compact_flags(const uint8_t *__restrict
     if (stop && *stop) return;          // a later round of a stopped batch
     __shared__ int s_wave[4];
     __shared__ int s_base;
+    __shared__ int32_t s_buf[COMPACT_CAP];
     const int nchunks = (n + 15) >> 4;
     const int lane = lane_id(), wv = threadIdx.x >> 6;
+    int held = 0;                       // entries in s_buf (the same in every thread)
     for (int c0 = blockIdx.x * 256; c0 < nchunks; c0 += gridDim.x * 256) {
         const int c = c0 + threadIdx.x;
         unsigned bits = 0;
@@ -651,24 +669,24 @@ __global__ __launch_bounds__(256) void k_compact_flags(const uint8_t *__restrict
         }
         if (lane == 63) s_wave[wv] = incl;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int k = 0; k < 4; k++) {
-                const int t = s_wave[k];
-                s_wave[k] = tot;
-                tot += t;
-            }
-            s_base = tot ? atomicAdd(count, tot) : 0;
+        int before = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int t = s_wave[k];
+            if (k < wv) before += t;
+            tot += t;
         }
-        __syncthreads();
-        int pos = s_base + s_wave[wv] + incl - cnt;
+        if (held + tot > COMPACT_CAP) compact_flush(list, count, s_buf, held, &s_base);
+        int pos = held + before + incl - cnt;
         while (bits) {
             const int j = __ffs(bits) - 1;
             bits &= bits - 1;
-            list[pos++] = 16 * c + j;
+            s_buf[pos++] = 16 * c + j;
         }
+        held += tot;
         __syncthreads();
     }
+    compact_flush(list, count, s_buf, held, &s_base);
 }
 
 // Hub vertices of the round, one block each (the vertices the discharge or

@@ -16,25 +16,35 @@ struct GraphView {
     const int32_t *cap;    // [slots]
 };
 
-// Counters written by the kernels and read back by the host driver.
+// Counters written by the kernels and read back by the host driver.  Every
+// counter that many blocks of one launch add to (one atomic per block) sits on
+// a 256-byte line of its own (MF_HOT): device atomics on one line serialize,
+// about 12 ns each on MI355X, so counters sharing a line cost their sum and
+// counters on separate lines proceed in parallel.
+#define MF_HOT alignas(256)
 struct Ctl {
-    int32_t na;            // entries of the current working-set list
-    int32_t na2;           // size of the next working set (list entries or dense count)
-    int32_t nc;            // entries of the candidate list
-    int32_t nq[3];         // BFS frontier sizes, ring indexed by level % 3
+    MF_HOT int32_t na;     // entries of the current working-set list
+    MF_HOT int32_t na2;    // size of the next working set (list entries or dense count)
+    MF_HOT int32_t nc;     // entries of the candidate list
+    MF_HOT int32_t nq[3];  // BFS frontier sizes, ring indexed by level % 3
     int32_t nh[3];         // BFS hub-list sizes, ring indexed by level % 3
     int32_t err;           // validation error bits
-    int64_t work;          // relabel work of the round (sum of outdeg + beta)
-    int64_t pushes, relabels, scans;
-    int64_t dverts, dslots;    // vertices discharged and their slots (first pass)
-    int64_t mverts, mslots;    // vertices merged and their slots
-    int64_t gslots;            // slots examined by global-relabel levels
+    MF_HOT int64_t work;   // relabel work of the round (sum of outdeg + beta)
+    MF_HOT int64_t pushes;
+    MF_HOT int64_t relabels;
+    MF_HOT int64_t scans;
+    MF_HOT int64_t dverts;     // vertices discharged and their slots (first pass)
+    MF_HOT int64_t dslots;
+    MF_HOT int64_t mverts;     // vertices merged and their slots
+    MF_HOT int64_t mslots;
+    MF_HOT int64_t gslots;     // slots examined by global-relabel levels
     // results of a persistent phase launch
-    int64_t p_rounds, p_grs, p_levels, p_dense_rounds, p_bu_levels;
+    MF_HOT int64_t p_rounds;
+    int64_t p_grs, p_levels, p_dense_rounds, p_bu_levels;
     int32_t p_status, p_lists;
-    int64_t cut;           // cut capacity accumulator
+    MF_HOT int64_t cut;    // cut capacity accumulator
     int64_t value;         // scratch for the host
-    int64_t hslots;        // slots examined by hub expansions (host-driven levels)
+    MF_HOT int64_t hslots; // slots examined by hub expansions (host-driven levels)
     int32_t maxdeg_inner;  // largest out-degree over vertices other than s and t
     int32_t deg_s, deg_t;  // out-degrees of s and t
     int32_t bfs_empty_level;   // first top-down level of this relabel that found its frontier empty
@@ -46,12 +56,13 @@ struct Ctl {
     // hub vertices of a round (discharged / merged by a block each) and
     // the counters of the hub kernels
     int32_t nhd, nhm;
-    int64_t dh_verts, dh_slots, dh_pushes, mh_verts, mh_slots;
+    MF_HOT int64_t dh_verts;
+    int64_t dh_slots, dh_pushes, mh_verts, mh_slots;
     // global relabel: out-degree sum of each BFS frontier (ring by level % 3)
     // and of every vertex labelled so far (edge-based direction choice)
-    int64_t fdeg[3];
-    int64_t gr_found_deg;
-    int64_t td_slots;      // profiling: slots expanded by the top-down levels of a relabel
+    MF_HOT int64_t fdeg[3];
+    MF_HOT int64_t gr_found_deg;
+    MF_HOT int64_t td_slots;   // profiling: slots expanded by the top-down levels of a relabel
     int32_t inv_err;       // MF_CHECK_INVARIANTS: bits of the checks that failed (k_check_state)
 };
 

@@ -574,6 +574,7 @@ struct Solve {
     bool hub_kernels;          // some vertex other than s and t exceeds hubd
     int hub_grid;
     int maxgrid;
+    int rgrid;                 // cap on the grids of the round kernels (discharge, merge, flag compaction)
     int64_t avg_deg_ceil;
     int64_t dense_threshold;   // working sets larger than this run in dense mode
     int64_t bu_factor;         // bottom-up BFS level when frontier * bu_factor > unvisited
@@ -666,7 +667,7 @@ static void prepare_working_set(Solve &S, int count, bool have_list, bool &dense
     dense = (int64_t)count > S.dense_threshold;
     if (!dense && !have_list) {
         (void)hipMemsetAsync(&S.ctx->ctl->na, 0, sizeof(int32_t), S.ctx->stream);
-        launch_compact_flags(S.st.act, S.g.n, S.st.A, &S.ctx->ctl->na, S.maxgrid, S.ctx->stream);
+        launch_compact_flags(S.st.act, S.g.n, S.st.A, &S.ctx->ctl->na, S.rgrid, S.ctx->stream);
     }
 }
 
@@ -942,9 +943,9 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             if (max_rounds > 0) K = (int)std::min<int64_t>(K, max_rounds - ps.rounds);
             const int groups = 256 / S.G;
             const int dgrid = grid_for(std::min<int64_t>(S.dense_threshold, 4 * (int64_t)na + 2048), groups,
-                                       S.maxgrid);
+                                       S.rgrid);
             const int mgrid = grid_for(std::min<int64_t>(S.dense_threshold, 4 * (int64_t)na + 2048) *
-                                           (1 + S.avg_deg_ceil), 256 / S.Gm, S.maxgrid);
+                                           (1 + S.avg_deg_ceil), 256 / S.Gm, S.rgrid);
             if (S.profile) {
                 mf_status est = batch_events(ctx, 8 * 16);
                 if (est != MF_OK) return est;
@@ -1037,8 +1038,8 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
         launch_round_reset(ctx->ctl, !list_ready, ctx->stream);
         const int groups = 256 / S.G;
         const int64_t na_room = K == 1 ? (int64_t)na : 2 * (int64_t)na;      // later rounds may grow
-        const int dgrid = grid_for(na_room, groups, S.maxgrid);
-        const int mgrid = grid_for(std::min<int64_t>(n, na_room * (1 + S.avg_deg_ceil)), 256 / S.Gm, S.maxgrid);
+        const int dgrid = grid_for(na_room, groups, S.rgrid);
+        const int mgrid = grid_for(std::min<int64_t>(n, na_room * (1 + S.avg_deg_ceil)), 256 / S.Gm, S.rgrid);
         if (S.profile) {
             mf_status est = batch_events(ctx, 12 * 8);
             if (est != MF_OK) return est;
@@ -1051,7 +1052,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
         for (int j = 0; j < K; j++) {
             const hipEvent_t *e = ctx->lev.data() + 12 * j;
             if (j == 0 && compact_first) {
-                launch_compact_flags(sj.act, (int)n, sj.A, &ctx->ctl->na, S.maxgrid, ctx->stream,
+                launch_compact_flags(sj.act, (int)n, sj.A, &ctx->ctl->na, S.rgrid, ctx->stream,
                        kev(S, MF_K_COMPACT, e, 0));
             }
             launch_discharge(S.G, true, S.g, sj, rp, dgrid, ctx->stream,
@@ -1060,7 +1061,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                 launch_discharge_hubs(true, S.g, sj, rp, S.hub_grid, ctx->stream,
                        kev(S, MF_K_DISCHARGE_HUB, e, 4));
             }
-            launch_compact_flags(sj.touched, (int)n, sj.C, &ctx->ctl->nc, S.maxgrid, ctx->stream,
+            launch_compact_flags(sj.touched, (int)n, sj.C, &ctx->ctl->nc, S.rgrid, ctx->stream,
                    kev(S, MF_K_COMPACT, e, 6), &ctx->ctl->batch_stop);
             launch_merge(S.Gm, true, S.g, sj, sink, other, S.hubd, mgrid, ctx->stream,
                    kev(S, MF_K_MERGE_DENSE, e, 8));
@@ -1387,8 +1388,12 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
     }
     S.Gm = o.lanes_per_merge > 0 ? pick_lanes(o.lanes_per_merge, 1, 1) : S.G;
     S.maxgrid = ctx->num_cus * 16;
+    // Round kernels end with one atomic per block on a few shared counters,
+    // which serialize (about 12 ns each): at most 4 blocks per compute unit,
+    // striding over the rest of the work.
+    S.rgrid = ctx->num_cus * (!(o.flags & MF_PERSISTENT) && o.blocks_per_cu > 0 ? o.blocks_per_cu : 4);
     S.avg_deg_ceil = (dg->slots + dg->n - 1) / std::max<int64_t>(1, dg->n);
-    S.dense_threshold = std::min<int64_t>(65536, std::max<int64_t>(2048, dg->n / 512));
+    S.dense_threshold = std::min<int64_t>(65536, std::max<int64_t>(2048, dg->n / 256));
     S.bu_factor = o.bfs_bottom_up_factor > 0 ? o.bfs_bottom_up_factor : 8;
     S.hubdeg = 64 * S.Gb;
     // Rounds discharge and merge vertices other than s and t only (a push
@@ -1412,8 +1417,8 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
     else
         launch_init_state(S.g, S.st, grid_for(std::max<int64_t>(dg->slots, n), 256, S.maxgrid), ctx->stream);
     launch_saturate(S.g, S.st, ctx->num_cus * 4, ctx->stream);
-    launch_compact_flags(S.st.touched, n, S.st.C, &ctx->ctl->nc, S.maxgrid, ctx->stream);
-    launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, S.hubd, grid_for(n, 256 / S.Gm, S.maxgrid), ctx->stream);
+    launch_compact_flags(S.st.touched, n, S.st.C, &ctx->ctl->nc, S.rgrid, ctx->stream);
+    launch_merge(S.Gm, true, S.g, S.st, dg->t, dg->s, S.hubd, grid_for(n, 256 / S.Gm, S.rgrid), ctx->stream);
     if (S.hub_kernels) launch_merge_hubs(true, S.g, S.st, dg->t, dg->s, S.hub_grid, ctx->stream);
 
     PhaseStats p1;
