@@ -122,6 +122,14 @@ typedef struct {
                                   distances are valid labels, Sec. 2.1).  Rounds run one per
                                   read-back in this mode, and the grid-wide kernels solve
                                   every graph */
+#define MF_GAP_RELABEL  0x80u  /* the gap rule at the end of every round (Sec. 3 names gap
+                                  relabeling, after Cherkassky and Goldberg, Ch. 3): when no
+                                  vertex other than the terminals holds some label k in (0, n)
+                                  while some hold larger ones, every label in (k, n) becomes n,
+                                  for the smallest such k.  Value, cut and sink side are the same;
+                                  rounds and per-slot flow differ.  Grid-wide kernels only
+                                  (small graphs use them too); not in the batched and served
+                                  forms, with MF_PERSISTENT or without allocation (MF_EINVAL) */
 #define MF_BATCH_GRID_SLOTS 262144
 #define MF_SMALL_N      8192
 #define MF_SMALL_SLOTS  16384
@@ -161,7 +169,11 @@ typedef struct {
     int32_t batch_grid_slots;    /* batched and served forms: an instance with more slots than this
                                     is solved by the grid-wide kernels (one instance at a time, the
                                     whole device) instead of one workgroup (0 = MF_BATCH_GRID_SLOTS) */
-    int32_t reserved;
+    int32_t block_round_max;     /* host-driven rounds: while the working set has at most this many
+                                    vertices, consecutive rounds run inside one workgroup with block
+                                    barriers instead of launches per round (the same rounds, so the
+                                    same results); 0 = automatic (256), negative = never.  Not used
+                                    on graphs with hub vertices or with MF_CHECK_INVARIANTS */
 } mf_options;
 
 typedef struct {
@@ -191,6 +203,8 @@ typedef struct {
     int64_t kernel_bytes[12];
     int64_t kernel_timed[12];    /* launches whose durations make up kernel_ms (all of them, or
                                     every profile_stride-th one) */
+    int64_t gap_lifts, gap_lifts2;   /* with MF_GAP_RELABEL: labels the gap rule set to n (phase 1,
+                                        phase 2) */
 } mf_stats;
 
 /* Kernels of the host-driven path that mf_stats profiles one by one.
@@ -219,7 +233,9 @@ typedef enum {
     MF_K_DISCHARGE_HUB = 8,
     MF_K_MERGE_HUB = 9,
     MF_K_BLOCK_SOLVE = 10,     /* a small graph's whole solve by one workgroup (no byte model) */
-    MF_K_COUNT = 11
+    MF_K_BLOCK_ROUNDS = 11,    /* rounds of a small working set in one workgroup (discharge and
+                                  merge bytes of those rounds) */
+    MF_K_COUNT = 12
 } mf_kernel_id;
 
 typedef struct mf_context mf_context;

@@ -27,6 +27,7 @@ MF_GRID_PATH = 0x8
 MF_SIMPLE_ROUNDS = 0x10
 MF_WARM_START = 0x20
 MF_CHECK_INVARIANTS = 0x40
+MF_GAP_RELABEL = 0x80
 
 
 class MaxflowError(RuntimeError):
@@ -52,7 +53,7 @@ class mf_options(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_bfs", ctypes.c_int32),
                 ("profile_mask", ctypes.c_uint32), ("bfs_bottom_up_factor", ctypes.c_int32),
                 ("profile_stride", ctypes.c_int32), ("check_fault_round", ctypes.c_int32),
-                ("batch_grid_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("batch_grid_slots", ctypes.c_int32), ("block_round_max", ctypes.c_int32)]
 
 
 class mf_stats(ctypes.Structure):
@@ -66,11 +67,13 @@ class mf_stats(ctypes.Structure):
         "merge_bytes", "global_relabel_bytes")] + [
         ("ms_phase_kernel", ctypes.c_double), ("phase_launches", ctypes.c_int64),
         ("kernel_ms", ctypes.c_double * 12), ("kernel_launches", ctypes.c_int64 * 12),
-        ("kernel_bytes", ctypes.c_int64 * 12), ("kernel_timed", ctypes.c_int64 * 12)]
+        ("kernel_bytes", ctypes.c_int64 * 12), ("kernel_timed", ctypes.c_int64 * 12),
+        ("gap_lifts", ctypes.c_int64), ("gap_lifts2", ctypes.c_int64)]
 
 # kernel names of mf_stats.kernel_* in index order (mf_kernel_id)
 KERNEL_NAMES = ("k_discharge_list", "k_discharge_dense", "k_merge_list", "k_merge_dense", "k_gr_td",
-                "k_gr_hub", "k_gr_bu", "k_compact_flags", "k_discharge_hubs", "k_merge_hubs", "k_batch")
+                "k_gr_hub", "k_gr_bu", "k_compact_flags", "k_discharge_hubs", "k_merge_hubs", "k_batch",
+                "k_rounds_block")
 
 
 class mf_result(ctypes.Structure):
@@ -170,6 +173,8 @@ def options(**kw) -> mf_options:
             o.flags = (o.flags | MF_SIMPLE_ROUNDS) if v else (o.flags & ~MF_SIMPLE_ROUNDS)
         elif k == "warm_start":
             o.flags = (o.flags | MF_WARM_START) if v else (o.flags & ~MF_WARM_START)
+        elif k == "gap":
+            o.flags = (o.flags | MF_GAP_RELABEL) if v else (o.flags & ~MF_GAP_RELABEL)
         elif k == "check_invariants":
             o.flags = (o.flags | MF_CHECK_INVARIANTS) if v else (o.flags & ~MF_CHECK_INVARIANTS)
         else:

@@ -785,6 +785,182 @@ __global__ void k_round_close(Ctl *ctl, int first, int64_t W0, int64_t charge, i
 }
 
 // ---------------------------------------------------------------------------
+// Gap rule (Sec. 3 names gap relabeling, after Cherkassky and Goldberg), at
+// the end of every round: the smallest label k in (0, n) that no vertex other
+// than the terminals holds while some hold larger labels is a gap, and every
+// label in (k, n) becomes n.  The merges keep the label histogram lcount and
+// list the labels whose count fell to 0 during the round (gcand); since the
+// rule leaves no hole behind, a gap can open only there.
+
+// The round's gap: the smallest candidate whose count is still 0 (n: none).
+__global__ __launch_bounds__(256) void k_gap_find(GraphView g, StateView st)
+{
+    Ctl *ctl = st.ctl;
+    if (ctl->batch_stop) return;
+    const int ngc = ctl->ngc;
+    int best = g.n;
+    for (int i = threadIdx.x; i < ngc; i += blockDim.x) {
+        const int k = st.gcand[i];
+        if (k > 0 && k < best && st.lcount[k] == 0) best = k;
+    }
+    __shared__ int sh[4];
+    for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+    if (lane_id() == 0) sh[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->gap = min(min(sh[0], sh[1]), min(sh[2], sh[3]));
+        ctl->ngc = 0;
+    }
+}
+
+// Lifts every label in (gap, n) to n (vertices other than the terminals);
+// they leave the working set.
+__global__ __launch_bounds__(256) void k_gap_lift(GraphView g, StateView st, int sink, int other)
+{
+    Ctl *ctl = st.ctl;
+    if (ctl->batch_stop) return;
+    const int gap = ctl->gap;
+    if (gap >= g.n) return;
+    const int stride = gridDim.x * blockDim.x;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t lifted = 0;
+    for (int v = tid; v < g.n; v += stride) {
+        const int d = st.d[v];
+        if (v != sink && v != other && d > gap && d < g.n) {
+            st.d[v] = g.n;
+            st.dn[v] = g.n;
+            st.act[v] = 0;
+            lifted++;
+        }
+    }
+    for (int k = gap + 1 + tid; k < g.n; k += stride) st.lcount[k] = 0;
+    block_add64(lifted, &ctl->gap_lifts);
+}
+
+// The next working set after the gap rule: the vertices merged this round
+// (list rounds: the candidate entries that own their vertex; dense rounds:
+// the listed touched vertices) that are active.
+__global__ __launch_bounds__(256) void k_gap_next(GraphView g, StateView st, int sink, int other, int dense)
+{
+    Ctl *ctl = st.ctl;
+    if (ctl->batch_stop) return;
+    const int nc = ctl->nc;
+    if ((int)(blockIdx.x * blockDim.x) >= nc) return;
+    MF_STAGE(stage);
+    stage_init(stage);
+    for (int base = blockIdx.x * blockDim.x; base < nc; base += gridDim.x * blockDim.x) {
+        const int i = base + threadIdx.x;
+        bool pa = false;
+        int w = 0;
+        if (i < nc) {
+            w = st.C[i];
+            if (dense || st.owner[w] == i)
+                pa = w != sink && w != other && st.e[w] > 0 && st.d[w] < g.n;
+        }
+        stage_append(stage, pa, w, st.A2, &ctl->na2);
+    }
+    stage_flush(stage, st.A2, &ctl->na2);
+}
+
+// The histogram after a global relabel (labels are exact distances then).
+__global__ __launch_bounds__(256) void k_gap_clear(GraphView g, StateView st)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= g.n; k += gridDim.x * blockDim.x) st.lcount[k] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st.ctl->ngc = 0;
+}
+__global__ __launch_bounds__(256) void k_gap_recount(GraphView g, StateView st, int sink, int other)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < g.n; base += stride) {
+        const int v = base + threadIdx.x;
+        const int d = v < g.n ? st.d[v] : g.n;
+        int amt;
+        (void)wave_count_add(v < g.n && v != sink && v != other && d < g.n, d, 1, st.lcount, &amt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rounds of small working sets in one workgroup.  While the working set stays
+// at or below `small_max` vertices, consecutive list rounds (the discharge
+// and the merge above, with the same counters) run inside one workgroup of
+// 1024 threads with block barriers between the steps, instead of three
+// launches and a share of a host read-back per round.  Each round is a
+// function of its start state, so the rounds are the ones the grid-wide
+// kernels would run.  The kernel stops, as k_round_close stops a batch of
+// speculative rounds, after the first round whose next working set is empty,
+// larger than small_max or the dense threshold, or after which W calls for a
+// global relabel, or when `budget` rounds have run; it leaves batch_rounds,
+// batch_W and batch_stop = 1 as a stopped batch does (the next working set
+// listed in the A2 of the stopping round).  Graphs with hub vertices do not
+// use it (their hubs take a block each in the grid-wide rounds).
+constexpr int BLOCK_ROUNDS_THREADS = 1024;
+
+template <int G>
+__global__ __launch_bounds__(BLOCK_ROUNDS_THREADS) void k_rounds_block(GraphView g, StateView st,
+                                                                      RoundParams p, int other, int64_t W0,
+                                                                      int64_t charge, int64_t freq_num,
+                                                                      int64_t freq_den, int64_t gr_threshold,
+                                                                      int64_t dense_threshold, int small_max,
+                                                                      int64_t budget)
+{
+    Ctl *ctl = st.ctl;
+    const int gl = threadIdx.x & (G - 1);
+    const int groups = blockDim.x / G;
+    MF_STAGE(stage);
+    int32_t *A = st.A, *A2 = st.A2;
+    int64_t W = W0;
+    int rounds = 0;
+    int na = ldc32(&ctl->na);
+    while (true) {
+        if (threadIdx.x == 0) {
+            ctl->nc = 0;
+            ctl->na2 = 0;
+            ctl->work = 0;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        StateView sr = st;
+        sr.A = A;
+        sr.A2 = A2;
+        DisAcc dacc;
+        for (int i = threadIdx.x / G; i < na; i += groups) discharge_vertex<G, false>(g, sr, p, A[i], gl, dacc);
+        discharge_flush(sr, p, dacc);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int nc = ldc32(&ctl->nc);
+        MerAcc macc;
+        stage_init(stage);
+        for (int i = threadIdx.x / G; i < nc; i += groups) {
+            const int w = st.C[i];
+            if (st.owner[w] != i) continue;
+            merge_vertex<G, false>(g, sr, w, gl, p.sink, other, macc, &stage);
+        }
+        stage_flush(stage, A2, &ctl->na2);
+        merge_flush(sr, false, macc);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        W += ldc64(&ctl->work) + charge;
+        rounds++;
+        const int next = ldc32(&ctl->na2);
+        const bool stop = next == 0 || next > small_max || next > dense_threshold ||
+                          freq_num * W > freq_den * gr_threshold || rounds >= budget;
+        if (stop) break;
+        int32_t *t = A;
+        A = A2;
+        A2 = t;
+        na = next;
+        __syncthreads();          // every thread has read the counters before they are reset
+    }
+    if (threadIdx.x == 0) {
+        ctl->batch_rounds = rounds;
+        ctl->batch_W = W;
+        ctl->batch_stop = 1;
+        ctl->na = na;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
 // Outputs.
 
 __global__ void k_side(GraphView g, const int32_t *__restrict__ d, uint8_t *__restrict__ side)
@@ -833,6 +1009,34 @@ __global__ void k_read_value(const int64_t *e, int t, Ctl *ctl) { ctl->value = e
         if ((EV).a) hipExtLaunchKernelGGL(K, dim3(GRID), dim3(256), 0, S, (EV).a, (EV).b, 0, __VA_ARGS__); \
         else hipLaunchKernelGGL(K, dim3(GRID), dim3(256), 0, S, __VA_ARGS__);                         \
     } while (0)
+
+#define MF_LAUNCH_T(K, GRID, THREADS, S, EV, ...)                                                 \
+    do {                                                                                              \
+        if ((EV).a) hipExtLaunchKernelGGL(K, dim3(GRID), dim3(THREADS), 0, S, (EV).a, (EV).b, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(K, dim3(GRID), dim3(THREADS), 0, S, __VA_ARGS__);                     \
+    } while (0)
+
+void launch_gap_round(GraphView g, StateView st, int sink, int other, int dense, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gap_find, dim3(1), dim3(256), 0, s, g, st);
+    hipLaunchKernelGGL(k_gap_lift, dim3(grid), dim3(256), 0, s, g, st, sink, other);
+    hipLaunchKernelGGL(k_gap_next, dim3(grid), dim3(256), 0, s, g, st, sink, other, dense);
+}
+void launch_gap_recount(GraphView g, StateView st, int sink, int other, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gap_clear, dim3(grid), dim3(256), 0, s, g, st);
+    hipLaunchKernelGGL(k_gap_recount, dim3(grid), dim3(256), 0, s, g, st, sink, other);
+}
+
+void launch_rounds_block(int G, GraphView g, StateView st, RoundParams p, int other, int64_t W0, int64_t charge,
+                         int64_t freq_num, int64_t freq_den, int64_t gr_threshold, int64_t dense_threshold,
+                         int small_max, int64_t budget, hipStream_t s, KEv ev)
+{
+#define C_(X) MF_LAUNCH_T((k_rounds_block<X>), 1, BLOCK_ROUNDS_THREADS, s, ev, g, st, p, other, W0, charge, \
+                          freq_num, freq_den, gr_threshold, dense_threshold, small_max, budget)
+    MF_DISPATCH_G(G, C_)
+#undef C_
+}
 
 void launch_discharge(int G, bool dense, GraphView g, StateView st, RoundParams p, int grid, hipStream_t s,
                       KEv ev)

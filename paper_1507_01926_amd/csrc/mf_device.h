@@ -64,6 +64,9 @@ struct Ctl {
     MF_HOT int64_t gr_found_deg;
     MF_HOT int64_t td_slots;   // profiling: slots expanded by the top-down levels of a relabel
     int32_t inv_err;       // MF_CHECK_INVARIANTS: bits of the checks that failed (k_check_state)
+    MF_HOT int32_t ngc;    // gap rule: candidate labels of the round
+    int32_t gap;           // gap rule: the round's gap (n: none)
+    MF_HOT int64_t gap_lifts;  // gap rule: labels set to n by it
 };
 
 // Parameters of a discharge step (host-built, passed to the kernels by value).
@@ -100,8 +103,23 @@ struct StateView {
     // carries its reverse edge's residual, the representation of Sec. 4.2).
     // Null where not provided; the levels then gather res[rev a].
     int32_t *hr;
+    // Gap rule (null when off): lcount[k] = number of vertices other than the
+    // terminals with label k < n; gcand lists the labels whose count fell to 0
+    // during the current round (ctl->ngc entries).
+    int32_t *lcount, *gcand;
     Ctl *ctl;
 };
+
+// Loads of counters other waves or blocks update with atomics: relaxed
+// agent-scope atomic loads, which never return a stale cached copy.
+__device__ __forceinline__ int ldc32(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t ldc64(const int64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------------------
 // Wave helpers (wave64).  A "group" is G consecutive lanes of a wave that
@@ -177,6 +195,42 @@ __device__ __forceinline__ int wave_append(bool pred, int32_t val, int32_t *list
         list[idx] = val;
     }
     return idx;
+}
+
+// Adds `delta` to lcount[key] for every calling lane with pred set, one
+// atomic per distinct key in the wave.  Returns, in the lane that made it,
+// the count before the atomic, else INT_MIN; *mine gets the amount that
+// atomic added.
+__device__ __forceinline__ int wave_count_add(bool pred, int key, int delta, int32_t *lcount, int *mine)
+{
+    uint64_t left = __ballot(pred);
+    int before = (int)0x80000000;
+    *mine = 0;
+    while (left) {
+        const int leader = __ffsll((unsigned long long)left) - 1;
+        const int k = __shfl(key, leader);
+        const uint64_t same = __ballot(pred && key == k) & left;
+        if (lane_id() == leader) {
+            *mine = delta * __popcll(same);
+            before = atomicAdd(&lcount[k], *mine);
+        }
+        left &= ~same;
+    }
+    return before;
+}
+
+// Gap rule, for a vertex whose label moves from dold to dnew at a round end:
+// the histogram follows, and a label whose count reaches 0 becomes a
+// candidate for the round's gap.  Every lane of the wave must call it.
+__device__ __forceinline__ void gap_relabel_count(const StateView &st, bool moved, int dold, int dnew, int n)
+{
+    int amt;
+    const int before = wave_count_add(moved, dold, -1, st.lcount, &amt);
+    if (before != (int)0x80000000 && before + amt == 0 && dold > 0) {
+        const int i = atomicAdd(&st.ctl->ngc, 1);
+        st.gcand[i] = dold;
+    }
+    (void)wave_count_add(moved && dnew < n, dnew, 1, st.lcount, &amt);
 }
 
 // Position of the k-th (0-based) set bit of m; k < popcount(m).

@@ -45,6 +45,7 @@ struct Workspace {
     uint8_t *act = nullptr, *side = nullptr, *touched = nullptr;
     int32_t *A = nullptr, *A2 = nullptr, *C = nullptr, *Q = nullptr, *Q2 = nullptr, *H = nullptr;
     int32_t *hr = nullptr;   // packed heads of the top-down search (null: gather reverse residuals)
+    int32_t *lcount = nullptr, *gcand = nullptr;   // gap rule: label histogram [n+1], candidates [n]
     size_t bytes = 0;
 };
 

@@ -200,14 +200,22 @@ __device__ __forceinline__ void merge_vertex(const GraphView &g, StateView &st, 
     }
     sum = group_sum<G>(sum);
     bool pa = false;
+    int dold = 0, dnew = 0;
     if (gl == 0) {
         const int64_t e = st.e[w] + sum;
         st.e[w] = e;
-        const int dnew = st.dn[w];
+        dnew = st.dn[w];
+        dold = st.d[w];
         st.d[w] = dnew;
         pa = w != sink && w != other && e > 0 && dnew < g.n;
         st.act[w] = pa;
         if (DENSE) st.touched[w] = 0;
+    }
+    if (st.lcount) {
+        // gap rule: the next working set is listed after the round's gap
+        // has lifted its labels (k_gap_next)
+        gap_relabel_count(st, gl == 0 && dnew != dold, dold, dnew, g.n);
+        return;
     }
     // the next working set, listed in A2 (each vertex is merged once); with a
     // stage the entries collect in LDS and the caller flushes them
@@ -412,14 +420,20 @@ __device__ __forceinline__ void merge_hub(const GraphView &g, StateView &st, int
     int64_t tot;
     (void)block_incl_scan64(sum, tot, sh64);
     bool pa = false;
+    int dold = 0, dnew = 0;
     if (tid == 0) {
         const int64_t e = st.e[w] + tot;
         st.e[w] = e;
-        const int dnew = st.dn[w];
+        dnew = st.dn[w];
+        dold = st.d[w];
         st.d[w] = dnew;
         pa = w != sink && w != other && e > 0 && dnew < g.n;
         st.act[w] = pa;
         if (DENSE) st.touched[w] = 0;
+    }
+    if (st.lcount) {
+        if (threadIdx.x < 64) gap_relabel_count(st, tid == 0 && dnew != dold, dold, dnew, g.n);
+        return;
     }
     stage_append(sg, pa, w, st.A2, &st.ctl->na2);
 }

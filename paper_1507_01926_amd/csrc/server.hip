@@ -355,7 +355,8 @@ extern "C" mf_status mf_server_submit(mf_server *sv, const mf_graph *g, const mf
                           (int64_t)g->n + g->slots < 2147483647LL && g->s >= 0 && g->s < g->n && g->t >= 0 &&
                           g->t < g->n && g->s != g->t && g->offsets && (g->slots == 0 || (g->head && g->rev && g->cap)) &&
                           o.gr_freq_den > 0 && o.gr_freq_num >= 0 && o.gr_alpha >= 0 && o.gr_beta >= 0 &&
-                          o.gr_round_charge >= 0 && o.gr_level_charge >= 0 && o.max_rounds >= 0;
+                          o.gr_round_charge >= 0 && o.gr_level_charge >= 0 && o.max_rounds >= 0 &&
+                          !(o.flags & (MF_GAP_RELABEL | MF_CHECK_INVARIANTS));
     if (shape_ok) {
         r->G = batch_lanes(o.lanes_per_vertex, g->n, g->slots);
         r->queue = 0;        // one queue; the serve kernel handles every lane count

@@ -69,6 +69,11 @@ void launch_cut(GraphView g, const uint8_t *side, Ctl *ctl, int grid, hipStream_
 void launch_flow(GraphView g, const int32_t *res, int32_t *flow, int grid, hipStream_t s);
 void launch_read_value(const int64_t *e, int t, Ctl *ctl, hipStream_t s);
 void launch_check_state(GraphView g, StateView st, int sink, int other, int after_gr, int grid, hipStream_t s);
+void launch_gap_round(GraphView g, StateView st, int sink, int other, int dense, int grid, hipStream_t s);
+void launch_gap_recount(GraphView g, StateView st, int sink, int other, int grid, hipStream_t s);
+void launch_rounds_block(int G, GraphView g, StateView st, RoundParams p, int other, int64_t W0, int64_t charge,
+                         int64_t freq_num, int64_t freq_den, int64_t gr_threshold, int64_t dense_threshold,
+                         int small_max, int64_t budget, hipStream_t s, KEv ev);
 void launch_bump(int32_t *p, hipStream_t s);
 
 
@@ -216,7 +221,7 @@ void mf_context_destroy(mf_context *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     Workspace &w = ctx->ws;
     void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.touched,
-                    w.A, w.A2, w.C, w.Q, w.Q2, w.H, w.hr};
+                    w.A, w.A2, w.C, w.Q, w.Q2, w.H, w.hr, w.lcount, w.gcand};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
@@ -489,7 +494,7 @@ static mf_status ensure_workspace(mf_context *ctx, int64_t n, int64_t slots)
     if (w.n_cap >= n && w.s_cap >= slots && w.res) return MF_OK;
     // release the old one
     void *ptrs[] = {w.res, w.delta, w.d, w.dn, w.owner, w.e, w.act, w.side, w.touched,
-                    w.A, w.A2, w.C, w.Q, w.Q2, w.H, w.hr};
+                    w.A, w.A2, w.C, w.Q, w.Q2, w.H, w.hr, w.lcount, w.gcand};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     ctx->used -= std::min(ctx->used, w.bytes);
@@ -513,6 +518,8 @@ static mf_status ensure_workspace(mf_context *ctx, int64_t n, int64_t slots)
     if ((st = dalloc(ctx, (void **)&w.H, 4 * N)) != MF_OK) return st;
     if ((st = dalloc(ctx, (void **)&w.touched, N)) != MF_OK) return st;
     if ((st = dalloc(ctx, (void **)&w.hr, 4 * S)) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.lcount, 4 * (N + 1))) != MF_OK) return st;
+    if ((st = dalloc(ctx, (void **)&w.gcand, 4 * N)) != MF_OK) return st;
     w.n_cap = N;
     w.s_cap = S;
     w.bytes = ctx->used - before;
@@ -585,6 +592,8 @@ struct Solve {
     uint32_t pmask;            // kernels (bits of mf_kernel_id) timed with events under MF_PROFILE
     bool persistent;
     bool check;                // MF_CHECK_INVARIANTS: state checks after every round and global relabel
+    int block_small_max;       // working sets up to this size run their rounds in one workgroup (0 = never)
+    bool gap;                  // MF_GAP_RELABEL: the gap rule after every round
     bool fault_done = false;   // the check_fault_round test hook has fired
     // profiling accumulators
     double ms_dis = 0, ms_mer = 0, ms_gr = 0, ms_phase = 0;
@@ -883,6 +892,7 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
         }
     }
     launch_gr_rebuild(S.g, S.st, sink, other, grid_for(n, 256, S.maxgrid), ctx->stream);
+    if (S.gap) launch_gap_recount(S.g, S.st, sink, other, grid_for(n, 256, S.rgrid), ctx->stream);
     mf_status st = read_ctl(ctx);
     if (st != MF_OK) return st;
     if (S.profile) {
@@ -935,6 +945,45 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
             continue;
         }
         if (max_rounds > 0 && ps.rounds >= max_rounds) return MF_ETIMEOUT;
+        if (!dense && na <= S.block_small_max) {
+            // a small working set: its rounds inside one workgroup, until
+            // one of them stops it as a stopped batch of list rounds
+            // (at most 65,536 rounds per launch: the launch returns at a round
+            // boundary and the host goes on from there)
+            const int64_t budget = std::min<int64_t>(65536, max_rounds > 0 ? max_rounds - ps.rounds : INT64_MAX);
+            if (S.profile) {
+                mf_status est = batch_events(ctx, 2);
+                if (est != MF_OK) return est;
+            }
+            launch_rounds_block(S.G, S.g, S.st, rp, other, W, o.gr_round_charge, o.gr_freq_num, o.gr_freq_den,
+                                o.gr_alpha * n + m + o.gr_level_charge * S.gr_depth, S.dense_threshold,
+                                S.block_small_max, budget, ctx->stream, kev(S, MF_K_BLOCK_ROUNDS, ctx->lev.data(), 0));
+            mf_status st = read_ctl(ctx);
+            if (st != MF_OK) return st;
+            const Ctl &c = *ctx->ctl_host;
+            const int r = c.batch_rounds;
+            W = c.batch_W;
+            ps.rounds += r;
+            if ((r - 1) & 1) std::swap(S.st.A, S.st.A2);   // the rounds before the stopping one
+            if (S.profile) {
+                int64_t b[4];
+                round_bytes(S, c, b);
+                const double ms = span(S, MF_K_BLOCK_ROUNDS, ctx->lev.data(), 0, 1);
+                kernel_record(S, MF_K_BLOCK_ROUNDS, ms, b[0] + b[2]);
+                S.ms_dis += timed_ms(ms);
+                S.n_dis += r;
+                S.n_mer += r;
+                S.last = c;
+            }
+            const int count = c.na2;
+            dense = count > S.dense_threshold;
+            launch_round_end(ctx->ctl, ctx->stream);   // na = na2
+            std::swap(S.st.A, S.st.A2);
+            list_ready = true;
+            na = count;
+            rbatch = 1;
+            continue;
+        }
         if (!dense) {
             // Speculative list rounds: up to `rbatch` rounds with one readback;
             // the round that must be followed by a global relabel, a dense
@@ -969,6 +1018,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                     launch_merge_hubs(false, S.g, sj, sink, other, S.hub_grid, ctx->stream,
                            kev(S, MF_K_MERGE_HUB, e, q + 6));
                 }
+                if (S.gap) launch_gap_round(S.g, sj, sink, other, 0, S.rgrid, ctx->stream);
                 launch_round_close(ctx->ctl, j == 0, W, o.gr_round_charge, o.gr_freq_num, o.gr_freq_den,
                                    o.gr_alpha * n + m + o.gr_level_charge * S.gr_depth, S.dense_threshold,
                                    ctx->stream);
@@ -1069,6 +1119,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                 launch_merge_hubs(true, S.g, sj, sink, other, S.hub_grid, ctx->stream,
                        kev(S, MF_K_MERGE_HUB, e, 10));
             }
+            if (S.gap) launch_gap_round(S.g, sj, sink, other, 1, S.rgrid, ctx->stream);
             launch_round_close(ctx->ctl, j == 0, W, o.gr_round_charge, o.gr_freq_num, o.gr_freq_den,
                                o.gr_alpha * n + m + o.gr_level_charge * S.gr_depth, S.dense_threshold,
                                ctx->stream, 1);
@@ -1346,14 +1397,17 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
                                     "still hold its flow)");
     if ((o.flags & MF_CHECK_INVARIANTS) && (o.flags & MF_PERSISTENT))
         return fail(ctx, MF_EINVAL, "MF_CHECK_INVARIANTS runs the host-driven rounds: not with MF_PERSISTENT");
-    if (ext && ((warm && !resume) || (o.flags & MF_PROFILE)))
-        return fail(ctx, MF_EINVAL, "MF_WARM_START and MF_PROFILE are not available without allocation");
+    if (ext && ((warm && !resume) || (o.flags & (MF_PROFILE | MF_GAP_RELABEL))))
+        return fail(ctx, MF_EINVAL, "MF_WARM_START, MF_PROFILE and MF_GAP_RELABEL are not available without allocation");
+    if ((o.flags & MF_GAP_RELABEL) && (o.flags & MF_PERSISTENT))
+        return fail(ctx, MF_EINVAL, "MF_GAP_RELABEL runs the host-driven rounds: not with MF_PERSISTENT");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     if (!ext) {
         ctx->warm_dg = nullptr;       // the workspace is about to change
         if ((st = ensure_workspace(ctx, dg->n, dg->slots)) != MF_OK) return st;
     }
-    if (!ext && !warm && !(o.flags & (MF_PERSISTENT | MF_GRID_PATH | MF_CHECK_INVARIANTS)) && dg->n <= MF_SMALL_N &&
+    if (!ext && !warm && !(o.flags & (MF_PERSISTENT | MF_GRID_PATH | MF_CHECK_INVARIANTS | MF_GAP_RELABEL)) &&
+        dg->n <= MF_SMALL_N &&
         dg->slots <= MF_SMALL_SLOTS)
         return solve_small(ctx, dg, o, value, flow_dev, side_dev, stats);
 
@@ -1407,6 +1461,11 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
     S.stride = o.profile_stride > 1 ? o.profile_stride : 1;
     S.persistent = (o.flags & MF_PERSISTENT) != 0;
     S.check = (o.flags & MF_CHECK_INVARIANTS) != 0;
+    S.gap = (o.flags & MF_GAP_RELABEL) != 0;
+    S.st.lcount = S.gap ? w.lcount : nullptr;
+    S.st.gcand = S.gap ? w.gcand : nullptr;
+    S.block_small_max = (o.block_round_max < 0 || S.check || S.hub_kernels || S.gap) ? 0
+                        : (o.block_round_max > 0 ? o.block_round_max : 256);
     if (o.dense_threshold > 0) S.dense_threshold = o.dense_threshold;
 
     const int n = dg->n;
@@ -1431,6 +1490,7 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
     if ((st = read_ctl(ctx)) != MF_OK) return st;
     const int64_t pushes = ctx->ctl_host->pushes + cum[0], relabels = ctx->ctl_host->relabels + cum[1],
                   scans = ctx->ctl_host->scans + cum[2];
+    const int64_t lifts1 = ctx->ctl_host->gap_lifts;
 
     // value, sink side and cut capacity of the maximum preflow (the labels are
     // exact distances to t here)
@@ -1473,6 +1533,8 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
         (void)hipEventElapsedTime(&ms2, ctx->ev[0], ctx->ev[2]);
         stats->ms_preflow = ms1;
         stats->ms_total = ms2;
+        stats->gap_lifts = lifts1;
+        stats->gap_lifts2 = ctx->ctl_host->gap_lifts - lifts1;
         if (S.profile) {
             // Algorithmic bytes per unit of work:
             //  discharge: 40 B per discharged vertex (list entry or flag, two
@@ -1780,6 +1842,7 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
                     g.s >= 0 && g.s < g.n && g.t >= 0 && g.t < g.n && g.s != g.t && g.offsets &&
                     (g.slots == 0 || (g.head && g.rev && g.cap)) && check_options(ctx, &o[i]) == MF_OK;
         if (good && (o[i].flags & MF_PREFLOW_ONLY) && flows && flows[i]) good = false;
+        if (o[i].flags & (MF_GAP_RELABEL | MF_CHECK_INVARIANTS)) good = false;   // host-driven rounds only
         if (!good) {
             ok[i] = 0;
             results[i].status = MF_EINVAL;
