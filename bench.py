@@ -133,87 +133,163 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
 
 
-def stream_leg(count: int, n_hi: float, seed_note: str) -> dict:
+def _gen_instance(args):
+    """Pool worker: stream instance i as plain arrays (no GPU in the workers)."""
+    i, n_hi = args
+    from workloads import stream_instance
+    g = stream_instance(i, n_hi=n_hi)
+    return i, g
+
+
+def _instances(count: int, n_hi: float, procs: int, ahead: int = 96):
+    """Stream instances 0 .. count-1 in order, generated by a pool of worker
+    processes at most `ahead` instances ahead of their use (the whole stream
+    does not fit host memory at 1e6 vertices: about 190 GB of arrays)."""
+    if procs <= 1:
+        from workloads import stream_instance
+        for i in range(count):
+            yield i, stream_instance(i, n_hi=n_hi)
+        return
+    import collections
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")          # the workers never touch the GPU
+    with ctx.Pool(procs) as pool:
+        window = collections.deque()
+        nxt = 0
+        while nxt < count and len(window) < ahead:
+            window.append(pool.apply_async(_gen_instance, ((nxt, n_hi),)))
+            nxt += 1
+        while window:
+            i, g = window.popleft().get()
+            if nxt < count:
+                window.append(pool.apply_async(_gen_instance, ((nxt, n_hi),)))
+                nxt += 1
+            yield i, g
+
+
+def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs: int = 0,
+               oracle_every: int = 0) -> dict:
     """Batched and served forms on a stream of `count` instances (family
     uniform over the five generator rules, n log-uniform in [1e3, n_hi]),
-    with knobs from the autotuner, next to the plain solver run one request
-    at a time in arrival order."""
+    with the lane knob from the autotuner, next to the plain solver run one
+    request at a time in arrival order.  Instances are generated by a pool
+    of worker processes ahead of their use; the closed-loop batched form
+    takes them in chunks of `chunk` (each chunk one mf_batch_solve call, the
+    chunks one after another), the served form at their Poisson arrival
+    times (a request waits for its instance to be generated if the pool
+    falls behind: its latency counts from its actual submission)."""
     import numpy as np
     import paper_1507_01926_amd as mf
-    from paper_1507_01926_amd.autotune import Autotuner
-    from workloads import stream_instance, stream_arrivals
+    from paper_1507_01926_amd.autotune import Autotuner, bucket_of
+    from workloads import stream_arrivals
 
-    t0 = time.perf_counter()
-    graphs = [stream_instance(i, n_hi=n_hi) for i in range(count)]
-    gen_s = time.perf_counter() - t0
-    arcs = sum(g.m_arcs for g in graphs)
+    procs = procs or min(15, max(1, (os.cpu_count() or 2) - 1))
     ctx = mf.Context(0)
     tuner = Autotuner(ctx, cache_path=None)
-    # tune on one sample per bucket (the knobs never change results)
-    seen, sample = set(), []
-    from paper_1507_01926_amd.autotune import bucket_of
-    for g in graphs:
-        b = bucket_of(g)
-        if b not in seen:
-            seen.add(b)
-            sample.append(g)
-    t0 = time.perf_counter()
-    tuner.tune(sample, mode="batch", reps=1, round_divisors=(0, 128, 32))
-    tune_s = time.perf_counter() - t0
-    opts = [tuner.options_for(g, "batch") for g in graphs]
-    # warm-up, then closed loop: every request present at t = 0
-    mf.batch_solve(ctx, graphs[: min(8, count)], opts=opts[: min(8, count)], want_flow=False)
-    t0 = time.perf_counter()
-    res, ms_dev = mf.batch_solve(ctx, graphs, opts=opts, want_flow=True, want_side=True)
-    closed_s = time.perf_counter() - t0
-    assert all(r["status"] == 0 for r in res)
-    batched = {"solves_per_s": count / closed_s, "arcs_per_s": arcs / closed_s,
-               "p50_ms": _pct([r["ms_end"] for r in res], 50), "p99_ms": _pct([r["ms_end"] for r in res], 99),
-               "wall_s": closed_s, "device_ms": ms_dev,
-               "note": "latency = completion time from the batch start (all requests at t=0)"}
-    # plain solver, one request at a time: service times
-    service = []
-    plain_vals = []
-    for g, o in zip(graphs, opts):
-        t1 = time.perf_counter()
-        r = ctx.solve(g, o)
-        service.append(time.perf_counter() - t1)
-        plain_vals.append(r["value"])
-    assert plain_vals == [r["value"] for r in res]
+    t_all = time.perf_counter()
+    # closed loop: every request present at t = 0, processed in chunks
+    done_ms, plain_ms, values, plain_vals, arcs, fam = [], [], [], [], 0, {}
+    t_gpu = 0.0
+    buf = []
+    tuned = set()
+    checked = []
+    tune_s = 0.0
+
+    def flush(buf):
+        nonlocal t_gpu, tune_s
+        graphs = [g for _, g in buf]
+        fresh = []
+        # one autotuning sample per new bucket (knobs never change results)
+        for g in graphs:
+            b = bucket_of(g)
+            if b not in tuned:
+                tuned.add(b)
+                if g.slots <= 262144:
+                    fresh.append(g)
+        if fresh:
+            t0 = time.perf_counter()
+            tuner.tune(fresh, mode="batch", reps=1, round_divisors=(0, 128, 32))
+            tune_s += time.perf_counter() - t0
+        opts = [tuner.options_for(g, "batch") for g in graphs]
+        t0 = time.perf_counter()
+        res, _ = mf.batch_solve(ctx, graphs, opts=opts, want_flow=False, want_side=False)
+        dt = time.perf_counter() - t0
+        for r in res:
+            assert r["status"] == 0
+            done_ms.append(1e3 * t_gpu + r["ms_end"])
+            values.append(r["value"])
+        t_gpu += dt
+        for g, o in zip(graphs, opts):
+            t1 = time.perf_counter()
+            pr = ctx.solve(g, o, want_flow=False, want_side=False)
+            plain_ms.append(1e3 * (time.perf_counter() - t1))
+            plain_vals.append(pr["value"])
+
+    for i, g in _instances(count, n_hi, procs):
+        arcs += g.m_arcs
+        fam[g.family] = fam.get(g.family, 0) + 1
+        if oracle_every and i % oracle_every == 0 and g.n <= 2e5:
+            import oracle
+            checked.append((i, oracle.fifo_maxflow(g, preflow_only=True)["value"]))
+        buf.append((i, g))
+        if len(buf) == chunk:
+            flush(buf)
+            buf = []
+        if i % 256 == 255:
+            print(f"[bench] stream closed loop: {i + 1} instances", file=sys.stderr, flush=True)
+    if buf:
+        flush(buf)
+    assert plain_vals == values
+    for i, v in checked:
+        assert values[i] == v, (i, values[i], v)
+    closed_rate = count / t_gpu
+    batched = {"solves_per_s": closed_rate, "arcs_per_s": arcs / t_gpu,
+               "p50_ms": _pct(done_ms, 50), "p99_ms": _pct(done_ms, 99), "gpu_wall_s": t_gpu,
+               "note": f"latency = completion time from the stream start with every request present at t=0; "
+                       f"the stream runs as {-(-count // chunk)} mf_batch_solve calls of up to {chunk} "
+                       f"instances, one after another (generation time excluded)"}
     served = {}
+    plain_total_s = sum(plain_ms) / 1e3
     for frac in (0.5, 0.8):
-        rate = frac * count / closed_s
+        rate = frac * closed_rate
         arr = stream_arrivals(count, rate)
-        srv = mf.Server(ctx, hbm_budget_bytes=16 << 30)
-        tickets = []
+        srv = mf.Server(ctx, hbm_budget_bytes=64 << 30)
+        tickets, submit_late = [], 0
         t_start = time.perf_counter()
-        for i, g in enumerate(graphs):
+        for i, g in _instances(count, n_hi, procs):
             delay = arr[i] - (time.perf_counter() - t_start)
             if delay > 0:
                 time.sleep(delay)
-            tickets.append(srv.submit(g, opts[i]))
-        out = [srv.wait(t, 600000) for t in tickets]
+            elif delay < -0.005:
+                submit_late += 1
+            tickets.append(srv.submit(g, tuner.options_for(g, "batch"), want_flow=False))
+            if i % 512 == 511:
+                print(f"[bench] stream served {frac}x: {i + 1} submitted", file=sys.stderr, flush=True)
+        out = [srv.wait(t, 1800000) for t in tickets]
         span = time.perf_counter() - t_start
         st = srv.stats()
         srv.close()
-        assert [r["value"] for r in out] == plain_vals
+        assert [r["value"] for r in out] == values
         lat = [r["ms_latency"] for r in out]
-        # the plain solver on the same arrival trace, one at a time (FIFO)
         fin, plat = 0.0, []
-        for a, sv in zip(arr, service):
-            fin = max(fin, a) + sv
+        for a, sv in zip(arr, plain_ms):
+            fin = max(fin, a) + sv / 1e3
             plat.append(1e3 * (fin - a))
         served[f"poisson_{frac}x"] = {
             "rate_per_s": rate, "solves_per_s": count / span, "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
-            "peak_hbm_bytes": st["peak_bytes"], "kernel_launches": st["kernel_launches"],
+            "requests_submitted_late": submit_late, "peak_hbm_bytes": st["peak_bytes"],
+            "kernel_launches": st["kernel_launches"],
             "plain_one_at_a_time": {"solves_per_s": count / fin if fin else None,
                                     "p50_ms": _pct(plat, 50), "p99_ms": _pct(plat, 99)}}
     ctx.close()
     return {"stream": f"{count} instances, n log-uniform in [1e3, {n_hi:.0e}], families uniform over "
-                      f"the five generator rules ({seed_note})",
-            "arcs_total": arcs, "generate_s": gen_s, "autotune_s": tune_s,
-            "autotuned_buckets": len(sample), "batched": batched, "served": served,
-            "plain_one_at_a_time_solves_per_s": count / sum(service)}
+                      f"the five generator rules ({seed_note}); instances above "
+                      f"262,144 slots run on "
+                      f"the grid-wide kernels in both forms",
+            "families": fam, "arcs_total": arcs, "generator_processes": procs,
+            "autotune_s": tune_s, "autotuned_buckets": len(tuned), "batched": batched, "served": served,
+            "plain_one_at_a_time_solves_per_s": count / plain_total_s,
+            "oracle_checked_instances": len(checked), "wall_s": time.perf_counter() - t_all}
 
 
 def schedule_options(g, knobs: dict) -> dict:
@@ -297,6 +373,10 @@ def main():
     ap.add_argument("--stream", type=int, default=256,
                     help="instances of the batched/served stream leg (0 = skip)")
     ap.add_argument("--stream-nmax", type=float, default=1e5)
+    ap.add_argument("--stream-chunk", type=int, default=256,
+                    help="instances per mf_batch_solve call of the closed-loop stream")
+    ap.add_argument("--stream-oracle-every", type=int, default=64,
+                    help="check every k-th stream instance (up to 2e5 vertices) against the CPU oracle")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the solves, copy a buffer of this size on the device (a dispatch of known "
                          "traffic that scales the HBM counters of a profiler run)")
@@ -428,7 +508,8 @@ def main():
     ctx.close()
     if args.stream > 0:
         print(f"[bench] stream leg x{args.stream}", file=sys.stderr, flush=True)
-        line["stream"] = stream_leg(args.stream, args.stream_nmax, "seeded")
+        line["stream"] = stream_leg(args.stream, args.stream_nmax, "seeded", chunk=args.stream_chunk,
+                                    oracle_every=args.stream_oracle_every)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline_leg(args.workload)

@@ -130,7 +130,7 @@ typedef struct {
                                   rounds and per-slot flow differ.  Grid-wide kernels only
                                   (small graphs use them too); not in the batched and served
                                   forms, with MF_PERSISTENT or without allocation (MF_EINVAL) */
-#define MF_BATCH_GRID_SLOTS 262144
+#define MF_BATCH_GRID_SLOTS 524288
 #define MF_SMALL_N      8192
 #define MF_SMALL_SLOTS  16384
 
@@ -174,6 +174,10 @@ typedef struct {
                                     barriers instead of launches per round (the same rounds, so the
                                     same results); 0 = automatic (256), negative = never.  Not used
                                     on graphs with hub vertices or with MF_CHECK_INVARIANTS */
+    int32_t grid_workers;        /* batched form: instances above the routing size are solved by this
+                                    many host threads at once, each with a stream of its own (0 = 4);
+                                    the first instance's value counts for the batch */
+    int32_t reserved;
 } mf_options;
 
 typedef struct {
@@ -369,8 +373,8 @@ typedef struct {
 /* Solves k graphs given in host memory, each by the method of
  * mf_solve_uploaded (Sec. 2, 2.1, 3.1).  Instances up to the routing size
  * (mf_options.batch_grid_slots) run in the persistent batch launch; larger
- * ones are solved after it, one at a time, by the grid-wide kernels (their
- * lanes_per_vertex result is 0).  opts is NULL (the defaults for all)
+ * ones are solved while it runs by the grid-wide kernels, grid_workers of
+ * them at a time (their lanes_per_vertex result is 0).  opts is NULL (the defaults for all)
  * or an array of k options (per-instance schedules, e.g. from the autotuner;
  * lanes_per_vertex 0 = automatic, otherwise 4, 8, 16 or 32).  flows[i] /
  * sides[i] are host buffers (int32[slots_i] / uint8[n_i]) or NULL, and flows
@@ -390,8 +394,8 @@ mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *graphs, con
  * as a workgroup is free; that workgroup pulls the graph from pinned host
  * memory and sends the results back itself).  A request with more slots than
  * the routing size (mf_options.batch_grid_slots) goes to a second lane that
- * solves one request at a time with the grid-wide kernels, beside the
- * persistent kernel, in a slice of the same budget.  Results are identical to
+ * solves such requests with the grid-wide kernels, grid_workers at a time,
+ * beside the persistent kernel, in slices of the same budget.  Results are identical to
  * mf_solve's for the same options.  All server calls are thread-safe.
  */
 typedef struct {
@@ -402,7 +406,10 @@ typedef struct {
     int32_t host_staging_mib;  /* pinned host memory through which graphs and results pass, in MiB
                                   (0 = the budget, at most 1 GiB); a request needs 8(n+1) + 16 slots
                                   bytes of it, each part rounded up to 256, while it is in flight */
-    int32_t reserved[4];
+    int32_t grid_workers;      /* requests above the routing size run on this many grid-lane threads
+                                  at once, each with a stream of its own (0 = 4); re-solves of
+                                  resident graphs run on the first */
+    int32_t reserved[3];
 } mf_server_config;
 
 typedef struct {

@@ -28,6 +28,7 @@ MF_SIMPLE_ROUNDS = 0x10
 MF_WARM_START = 0x20
 MF_CHECK_INVARIANTS = 0x40
 MF_GAP_RELABEL = 0x80
+MF_BATCH_GRID_SLOTS = 524288      # default routing size of the batched and served forms
 
 
 class MaxflowError(RuntimeError):
@@ -53,7 +54,8 @@ class mf_options(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_bfs", ctypes.c_int32),
                 ("profile_mask", ctypes.c_uint32), ("bfs_bottom_up_factor", ctypes.c_int32),
                 ("profile_stride", ctypes.c_int32), ("check_fault_round", ctypes.c_int32),
-                ("batch_grid_slots", ctypes.c_int32), ("block_round_max", ctypes.c_int32)]
+                ("batch_grid_slots", ctypes.c_int32), ("block_round_max", ctypes.c_int32),
+                ("grid_workers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mf_stats(ctypes.Structure):
@@ -87,7 +89,8 @@ class mf_result(ctypes.Structure):
 class mf_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
                 ("idle_ms", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("host_staging_mib", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("host_staging_mib", ctypes.c_int32), ("grid_workers", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class mf_server_stats(ctypes.Structure):
@@ -398,9 +401,9 @@ class Server:
     """An mf_server: admission by HBM budget, continuous batching, latency per request."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_inflight: int = 0, idle_ms: int = 0,
-                 blocks_per_cu: int = 0, host_staging_mib: int = 0):
+                 blocks_per_cu: int = 0, host_staging_mib: int = 0, grid_workers: int = 0):
         cfg = mf_server_config(int(hbm_budget_bytes), int(max_inflight), int(idle_ms), int(blocks_per_cu),
-                               int(host_staging_mib))
+                               int(host_staging_mib), int(grid_workers))
         h = ctypes.c_void_p()
         ctx._check(lib().mf_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
         self.ctx, self.h = ctx, h

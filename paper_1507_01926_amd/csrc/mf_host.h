@@ -63,6 +63,9 @@ struct mf_context {
     hipStream_t bstream[4] = {nullptr, nullptr, nullptr, nullptr};                 // batch groups
     hipEvent_t bev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t sev[2] = {nullptr, nullptr};   // ordering against a caller's stream (in, out)
+    hipStream_t lstream = nullptr;             // the batch launch, beside the grid-wide solves of large instances
+    hipEvent_t gev[2] = {nullptr, nullptr};    // start and end of the batch launch
+    std::vector<mf_context *> helpers;         // batched form: contexts of the grid-wide solve workers
     std::vector<hipEvent_t> lev;     // profiling of batched levels, created on first use
     Workspace ws;
     uint8_t *one = nullptr;    // device: item, result, queue and order of a single-workgroup solve

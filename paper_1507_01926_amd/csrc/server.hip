@@ -222,9 +222,10 @@ struct mf_server {
     mf_server_stats st;
     size_t bytes_in_use = 0;
     std::string err;
-    // grid lane
-    mf_context *gctx = nullptr;
-    std::thread gworker;
+    // grid lane: worker threads, each with a context of its own (worker 0
+    // also takes registrations and re-solves of resident graphs, in order)
+    std::vector<mf_context *> gctx;
+    std::vector<std::thread> gworkers;
     std::deque<Request *> gpending;
     std::mutex amu;                   // guards `alloc` (both workers carve the region)
     std::condition_variable acv;      // region space freed
@@ -234,7 +235,7 @@ struct mf_server {
 };
 
 static void server_loop(mf_server *sv);
-static void grid_loop(mf_server *sv);
+static void grid_loop(mf_server *sv, int wi);
 
 // Gives back what a request that will not be admitted holds on the host
 // side (called with the lock held).
@@ -302,9 +303,14 @@ extern "C" mf_status mf_server_create(mf_context *ctx, const mf_server_config *c
         return bail(MF_EDEVICE, "device counter allocation failed");
     sv->idle_ticks = ctx->wall_hz / 1000ull * (uint64_t)sv->cfg.idle_ms;
     for (int q = 0; q < 4; q++) sv->slot_owner[q].assign(SERVE_CAP, nullptr);
-    if (mf_context_create(ctx->device, 0, &sv->gctx) != MF_OK) return bail(MF_EDEVICE, "grid-lane context failed");
+    const int nw = sv->cfg.grid_workers > 0 ? std::min(sv->cfg.grid_workers, 32) : 4;
+    for (int w = 0; w < nw; w++) {
+        mf_context *gc = nullptr;
+        if (mf_context_create(ctx->device, 0, &gc) != MF_OK) return bail(MF_EDEVICE, "grid-lane context failed");
+        sv->gctx.push_back(gc);
+    }
     sv->worker = std::thread(server_loop, sv);
-    sv->gworker = std::thread(grid_loop, sv);
+    for (int w = 0; w < nw; w++) sv->gworkers.emplace_back(grid_loop, sv, w);
     *out = sv;
     return MF_OK;
 }
@@ -316,8 +322,9 @@ extern "C" void mf_server_destroy(mf_server *sv)
     sv->cv.notify_all();
     sv->acv.notify_all();
     if (sv->worker.joinable()) sv->worker.join();
-    if (sv->gworker.joinable()) sv->gworker.join();
-    if (sv->gctx) mf_context_destroy(sv->gctx);
+    for (auto &t : sv->gworkers)
+        if (t.joinable()) t.join();
+    for (auto g : sv->gctx) mf_context_destroy(g);
     for (auto &kv : sv->residents) delete kv.second;
     (void)hipSetDevice(sv->ctx->device);
     for (int q = 0; q < 4; q++)
@@ -954,9 +961,8 @@ static mf_status take_device_outputs(mf_context *g, Request *r, const uint8_t *s
     return he == hipSuccess ? MF_OK : MF_EDEVICE;
 }
 
-static void grid_solve(mf_server *sv, Request *r)
+static void grid_solve(mf_server *sv, mf_context *g, Request *r)
 {
-    mf_context *g = sv->gctx;
     const auto t0 = Clock::now();
     const GridSlice G = grid_slice(r->n, r->S, r->want_flow, false);
     size_t off;
@@ -991,9 +997,8 @@ static void grid_solve(mf_server *sv, Request *r)
     uncarve(sv, off, G.end);
 }
 
-static void grid_register(mf_server *sv, Request *r, Resident *res)
+static void grid_register(mf_server *sv, mf_context *g, Request *r, Resident *res)
 {
-    mf_context *g = sv->gctx;
     const GridSlice G = grid_slice(r->n, r->S, true, true);
     size_t off;
     if (!carve(sv, G.end, off)) {
@@ -1020,9 +1025,8 @@ static void grid_register(mf_server *sv, Request *r, Resident *res)
     r->result.status = st;
 }
 
-static void grid_resolve(mf_server *sv, Request *r, Resident *res)
+static void grid_resolve(mf_server *sv, mf_context *g, Request *r, Resident *res)
 {
-    mf_context *g = sv->gctx;
     const auto t0 = Clock::now();
     mf_stats ss;
     memset(&ss, 0, sizeof ss);
@@ -1083,46 +1087,56 @@ static void grid_resolve(mf_server *sv, Request *r, Resident *res)
     r->result.resumed = resumable ? 1 : 0;
 }
 
-static void grid_loop(mf_server *sv)
+static void grid_loop(mf_server *sv, int wi)
 {
     (void)hipSetDevice(sv->ctx->device);
+    mf_context *g = sv->gctx[(size_t)wi];
     while (!sv->stop) {
         Request *r = nullptr;
         Resident *res = nullptr;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             // free released resident graphs that no queued request names
-            for (auto it = sv->residents.begin(); it != sv->residents.end();) {
-                Resident *x = it->second;
-                if (x->released && x->pending == 0) {
-                    if (x->bytes) uncarve(sv, x->off, x->bytes);
-                    delete x;
-                    it = sv->residents.erase(it);
-                } else {
-                    ++it;
+            if (wi == 0)
+                for (auto it = sv->residents.begin(); it != sv->residents.end();) {
+                    Resident *x = it->second;
+                    if (x->released && x->pending == 0) {
+                        if (x->bytes) uncarve(sv, x->off, x->bytes);
+                        delete x;
+                        it = sv->residents.erase(it);
+                    } else {
+                        ++it;
+                    }
                 }
-            }
-            if (sv->gpending.empty()) {
+            // the first request this worker may take: worker 0 any, the
+            // others one-shot solves only (resident graphs stay in order)
+            auto pick = sv->gpending.end();
+            for (auto it = sv->gpending.begin(); it != sv->gpending.end(); ++it)
+                if (wi == 0 || (*it)->kind == SOLVE) {
+                    pick = it;
+                    break;
+                }
+            if (pick == sv->gpending.end()) {
                 sv->cv.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
             }
-            r = sv->gpending.front();
-            sv->gpending.pop_front();
+            r = *pick;
+            sv->gpending.erase(pick);
             r->state = ADMITTING;
             if (r->kind != SOLVE) {
                 auto it = sv->residents.find(r->graph_id);
                 res = it == sv->residents.end() ? nullptr : it->second;
             }
-            sv->grid_busy = 1;
+            sv->grid_busy++;
         }
         if (r->kind == SOLVE)
-            grid_solve(sv, r);
+            grid_solve(sv, g, r);
         else if (!res)
             r->result.status = MF_ENOTFOUND;
         else if (r->kind == REGISTER)
-            grid_register(sv, r, res);
+            grid_register(sv, g, r, res);
         else
-            grid_resolve(sv, r, res);
+            grid_resolve(sv, g, r, res);
         std::vector<int64_t>().swap(r->off);
         std::vector<int64_t>().swap(r->rev);
         std::vector<int32_t>().swap(r->head);
@@ -1130,7 +1144,7 @@ static void grid_loop(mf_server *sv)
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             if (res) res->pending--;
-            sv->grid_busy = 0;
+            sv->grid_busy--;
             if (r->kind != REGISTER) {
                 if (r->canceled) {
                     r->result.status = MF_ECANCELED;

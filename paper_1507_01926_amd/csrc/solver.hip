@@ -19,7 +19,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <string>
 #include <vector>
@@ -236,6 +238,10 @@ void mf_context_destroy(mf_context *ctx)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : ctx->sev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto ev : ctx->gev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->lstream) (void)hipStreamDestroy(ctx->lstream);
+    for (auto h : ctx->helpers) mf_context_destroy(h);
     for (auto ev : ctx->lev) (void)hipEventDestroy(ev);
     for (auto bs : ctx->bstream)
         if (bs) (void)hipStreamDestroy(bs);
@@ -1237,10 +1243,26 @@ static mf_status run_phase_persistent(Solve &S, int sink, int other, int64_t max
     return gc.p_status == 1 ? MF_ETIMEOUT : MF_OK;
 }
 
+// Helper contexts of the batched form's grid-wide solves (one per worker
+// thread).
+static mf_status ensure_helpers(mf_context *ctx, int count)
+{
+    while ((int)ctx->helpers.size() < count) {
+        mf_context *h = nullptr;
+        mf_status st = mf_context_create(ctx->device, 0, &h);
+        if (st != MF_OK) return fail(ctx, st, "helper context: %s", g_global_err.c_str());
+        ctx->helpers.push_back(h);
+    }
+    return MF_OK;
+}
+
 static mf_status ensure_batch_streams(mf_context *ctx)
 {
     for (auto &bs : ctx->bstream)
         if (!bs) HIPCHK(ctx, hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+    if (!ctx->lstream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->lstream, hipStreamNonBlocking));
+    for (auto &ev : ctx->gev)
+        if (!ev) HIPCHK(ctx, hipEventCreate(&ev));
     for (auto &ev : ctx->bev)
         if (!ev) HIPCHK(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     return MF_OK;
@@ -2033,69 +2055,113 @@ extern "C" mf_status mf_batch_solve(mf_context *ctx, int32_t k, const mf_graph *
         (void)hipGraphDestroy(graph);
         return dev_err(he, "hipGraphInstantiate");
     }
-    (void)hipEventRecord(ctx->ev[0], s0);
-    he = hipGraphLaunch(exec, s0);
-    (void)hipEventRecord(ctx->ev[2], s0);
-    if (he == hipSuccess) he = hipStreamSynchronize(s0);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    if (he != hipSuccess) return dev_err(he, "batch launch");
-    (void)hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]);
-    he = hipMemcpy(hr.data(), res_d, sizeof(BatchResult) * (size_t)k, hipMemcpyDeviceToHost);
-    if (he != hipSuccess) return dev_err(he, "batch results");
+    // the batch runs on its own stream while the large instances below run
+    // on the context's stream
+    (void)hipEventRecord(ctx->gev[0], ctx->lstream);
+    he = hipGraphLaunch(exec, ctx->lstream);
+    (void)hipEventRecord(ctx->gev[1], ctx->lstream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(hr.data(), res_d, sizeof(BatchResult) * (size_t)k, hipMemcpyDeviceToHost, ctx->lstream);
+    if (he != hipSuccess) {
+        (void)hipStreamSynchronize(ctx->lstream);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return dev_err(he, "batch launch");
     }
-    // Instances above the routing size: one after another by the grid-wide
-    // kernels (a workgroup per instance would take seconds on the largest),
-    // each over its own slice of the arena.
+    }
+    // Instances above the routing size: by the grid-wide kernels while the
+    // batch launch runs, grid_workers at a time (each worker a host thread
+    // with a helper context: its own stream and control block), each over
+    // its own slice of the arena.
     std::vector<char> big((size_t)k, 0);
-    for (int i : large) {
-        big[i] = 1;
-        const mf_graph &gh = graphs[i];
-        const InstLayout &L = lay[i];
-        const Ctl &c0 = hc[5 * (size_t)i];
-        mf_dgraph dg;
-        dg.n = gh.n;
-        dg.s = gh.s;
-        dg.t = gh.t;
-        dg.slots = gh.slots;
-        dg.off = (int32_t *)(arena + L.off);
-        dg.head = (int32_t *)(arena + L.head);
-        dg.rev = (int32_t *)(arena + L.rev);
-        dg.cap = (int32_t *)(arena + L.cap);
-        dg.maxdeg_inner = c0.maxdeg_inner;
-        dg.deg_s = c0.deg_s;
-        dg.deg_t = c0.deg_t;
-        Workspace w = workspace_in(arena, L, gh.n, gh.slots);
-        mf_options oi = o[i];
-        oi.flags &= ~(uint32_t)MF_PROFILE;
-        mf_stats sst;
-        int64_t val = 0;
-        const double t_in = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_launch).count();
-        mf_status sr = solve_uploaded(ctx, &dg, &oi, &val, L.flow ? (int32_t *)(arena + L.flow) : nullptr,
-                                      arena + L.side, &sst, &w);
-        mf_result &R = results[i];
-        R.status = sr;
-        R.lanes_per_vertex = 0;
-        R.value = sst.value;
-        R.cut_capacity = sst.cut_capacity;
-        R.rounds = sst.rounds;
-        R.rounds2 = sst.rounds2;
-        R.global_relabels = sst.global_relabels;
-        R.global_relabels2 = sst.global_relabels2;
-        R.bfs_levels = sst.bfs_levels;
-        R.pushes = sst.pushes;
-        R.relabels = sst.relabels;
-        R.ms_start = t_in;
-        R.ms_end = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_launch).count();
-        if (sr == MF_EDEVICE) {
+    for (int i : large) big[i] = 1;
+    std::vector<mf_status> lst((size_t)k, MF_OK);
+    if (!large.empty()) {
+        const int want = opts && opts[0].grid_workers > 0 ? opts[0].grid_workers : 4;
+        const int nw = std::max(1, std::min<int>(want, (int)large.size()));
+        mf_status hs = ensure_helpers(ctx, nw);
+        if (hs != MF_OK) {
+            if (any_small) (void)hipStreamSynchronize(ctx->lstream);
             release();
-            return sr;
+            return hs;
         }
-        const size_t S = (size_t)gh.slots, N = (size_t)gh.n;
-        he = hipSuccess;
-        if (flows && flows[i] && S && (sr == MF_OK)) he = hipMemcpy(flows[i], arena + L.flow, 4 * S, hipMemcpyDeviceToHost);
-        if (he == hipSuccess && sides && sides[i]) he = hipMemcpy(sides[i], arena + L.side, N, hipMemcpyDeviceToHost);
-        if (he != hipSuccess) return dev_err(he, "batch output copy");
+        std::atomic<int> next_large{0};
+        auto worker = [&](int wi) {
+            mf_context *hx = ctx->helpers[(size_t)wi];
+            (void)hipSetDevice(ctx->device);
+            while (true) {
+                const int q = next_large.fetch_add(1);
+                if (q >= (int)large.size()) break;
+                const int i = large[(size_t)q];
+                const mf_graph &gh = graphs[i];
+                const InstLayout &L = lay[i];
+                const Ctl &c0 = hc[5 * (size_t)i];
+                mf_dgraph dg;
+                dg.n = gh.n;
+                dg.s = gh.s;
+                dg.t = gh.t;
+                dg.slots = gh.slots;
+                dg.off = (int32_t *)(arena + L.off);
+                dg.head = (int32_t *)(arena + L.head);
+                dg.rev = (int32_t *)(arena + L.rev);
+                dg.cap = (int32_t *)(arena + L.cap);
+                dg.maxdeg_inner = c0.maxdeg_inner;
+                dg.deg_s = c0.deg_s;
+                dg.deg_t = c0.deg_t;
+                Workspace w = workspace_in(arena, L, gh.n, gh.slots);
+                mf_options oi = o[i];
+                oi.flags &= ~(uint32_t)MF_PROFILE;
+                mf_stats sst;
+                memset(&sst, 0, sizeof sst);
+                int64_t val = 0;
+                const double t_in =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_launch).count();
+                mf_status sr = solve_uploaded(hx, &dg, &oi, &val, L.flow ? (int32_t *)(arena + L.flow) : nullptr,
+                                              arena + L.side, &sst, &w);
+                const size_t S = (size_t)gh.slots, N = (size_t)gh.n;
+                hipError_t e2 = hipSuccess;
+                if (sr == MF_OK && flows && flows[i] && S)
+                    e2 = hipMemcpyAsync(flows[i], arena + L.flow, 4 * S, hipMemcpyDeviceToHost, hx->stream);
+                if (e2 == hipSuccess && sr != MF_EDEVICE && sides && sides[i])
+                    e2 = hipMemcpyAsync(sides[i], arena + L.side, N, hipMemcpyDeviceToHost, hx->stream);
+                if (e2 == hipSuccess) e2 = hipStreamSynchronize(hx->stream);
+                if (e2 != hipSuccess) sr = MF_EDEVICE;
+                mf_result &R = results[i];
+                R.status = sr;
+                R.lanes_per_vertex = 0;
+                R.value = sst.value;
+                R.cut_capacity = sst.cut_capacity;
+                R.rounds = sst.rounds;
+                R.rounds2 = sst.rounds2;
+                R.global_relabels = sst.global_relabels;
+                R.global_relabels2 = sst.global_relabels2;
+                R.bfs_levels = sst.bfs_levels;
+                R.pushes = sst.pushes;
+                R.relabels = sst.relabels;
+                R.ms_start = t_in;
+                R.ms_end =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_launch).count();
+                lst[(size_t)i] = sr;
+            }
+        };
+        std::vector<std::thread> th;
+        for (int wi = 1; wi < nw; wi++) th.emplace_back(worker, wi);
+        worker(0);
+        for (auto &t : th) t.join();
+        for (int i : large)
+            if (lst[(size_t)i] == MF_EDEVICE) {
+                if (any_small) (void)hipStreamSynchronize(ctx->lstream);
+                std::string e = ctx->helpers[0]->err;
+                release();
+                return fail(ctx, MF_EDEVICE, "grid-wide solve of a large batch instance failed: %s", e.c_str());
+            }
+    }
+    if (any_small) {
+        he = hipStreamSynchronize(ctx->lstream);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (he != hipSuccess) return dev_err(he, "batch launch");
+        (void)hipEventElapsedTime(&ms, ctx->gev[0], ctx->gev[1]);
     }
     int64_t t0 = INT64_MAX;
     for (int i = 0; i < k; i++)

@@ -59,11 +59,14 @@ def _same_as_oracle(r, g, B, tag):
         assert r[k] == B[k], (tag, k, r[k], B[k])
 
 
+ROUTE = 1 << 18        # routing size of these tests: every LARGE instance goes to the grid-wide kernels
+
+
 def test_batch_large_instances_match_oracle(ctx, large):
     import paper_1507_01926_amd as mf
     small = [make_config("c1"), make_config("c2", 64), make_config("c4a", 64)]
     graphs = [g for g, _ in large] + small
-    res, _ = mf.batch_solve(ctx, graphs)
+    res, _ = mf.batch_solve(ctx, graphs, opts=[mf.options(batch_grid_slots=ROUTE) for _ in graphs])
     for k, (g, B) in enumerate(large):
         assert res[k]["lanes_per_vertex"] == 0          # solved by the grid-wide kernels
         _same_as_oracle(res[k], g, B, f"batch large {k} {g.family}")
@@ -72,6 +75,17 @@ def test_batch_large_instances_match_oracle(ctx, large):
         r = res[len(large) + j]
         assert r["lanes_per_vertex"] > 0                # one workgroup each
         _same_as_oracle(r, g, B, f"batch small {j}")
+
+
+def test_batch_default_routing(ctx, large):
+    """With the default routing size, instances above it (R-MAT here) go to
+    the grid-wide kernels while the batch launch runs, the rest run in it."""
+    import paper_1507_01926_amd as mf
+    graphs = [g for g, _ in large]
+    res, _ = mf.batch_solve(ctx, graphs)
+    for k, (g, B) in enumerate(large):
+        assert (res[k]["lanes_per_vertex"] == 0) == (g.slots > mf.MF_BATCH_GRID_SLOTS)
+        _same_as_oracle(res[k], g, B, f"default routing {k} {g.family}")
 
 
 def test_batch_routing_size_does_not_change_results(ctx, large):
@@ -91,7 +105,7 @@ def test_server_large_requests_alone_and_in_mix(ctx, large):
     try:
         tickets = []
         for k, (g, _) in enumerate(large):
-            tickets.append(("L", k, srv.submit(g)))
+            tickets.append(("L", k, srv.submit(g, mf.options(batch_grid_slots=ROUTE))))
             tickets.append(("S", 2 * k, srv.submit(small[2 * k])))
             tickets.append(("S", 2 * k + 1, srv.submit(small[2 * k + 1])))
         mix = {}
@@ -106,7 +120,7 @@ def test_server_large_requests_alone_and_in_mix(ctx, large):
         # alone: the same requests one at a time
         for k in (0, 3):
             g, _ = large[k]
-            alone = srv.wait(srv.submit(g), 600000)
+            alone = srv.wait(srv.submit(g, mf.options(batch_grid_slots=ROUTE)), 600000)
             m = mix[("L", k)]
             assert alone["value"] == m["value"]
             assert (alone["flow"] == m["flow"]).all() and (alone["sink_side"] == m["sink_side"]).all()
