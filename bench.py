@@ -60,14 +60,8 @@ def fixed_schedule(g, level_charge: int = 0) -> dict:
 def kernel_source_sha() -> str:
     """sha256 over the HIP sources of the library (counters taken on other
     sources no longer describe the kernels)."""
-    import hashlib
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1507_01926_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(d, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
-    return h.hexdigest()
+    from paper_1507_01926_amd.profiling import source_sha
+    return source_sha()
 
 
 def measured_traffic(kernel: str, workload: str):

@@ -221,8 +221,10 @@ typedef struct {
  *     vertices): n per pass plus 4 per listed vertex;
  *   hub discharge / hub merge (a block per vertex of degree above 64 lanes
  *     per vertex): as discharge / merge, for the hub vertices;
- *   top-down level: 12 per frontier vertex, 12 per slot examined, 8 per
- *     vertex labelled;  hub expansion: 12 per hub, 12 per slot examined;
+ *   top-down level: 12 per frontier vertex (list entry, two offsets), 8 per
+ *     slot examined (packed head with the reverse-residual bit, neighbour's
+ *     label), 8 per vertex labelled;  hub expansion: 12 per hub, 12 per slot
+ *     examined;
  *   bottom-up level: 4 per vertex, 8 per unlabelled vertex, 12 per slot
  *     examined, 8 per vertex labelled. */
 typedef enum {

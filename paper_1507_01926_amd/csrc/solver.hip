@@ -902,7 +902,10 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
     mf_status st = read_ctl(ctx);
     if (st != MF_OK) return st;
     if (S.profile) {
-        S.kb[MF_K_GR_TOPDOWN] += 12 * ctx->ctl_host->td_slots;
+        // a top-down slot reads its packed head (4 B) and, for an open arc,
+        // the neighbour's label (4 B): 8 B counted per slot; without packed
+        // heads (head, reverse index, reverse residual, label) 16 B
+        S.kb[MF_K_GR_TOPDOWN] += (S.st.hr ? 8 : 16) * ctx->ctl_host->td_slots;
         S.td_slots += ctx->ctl_host->td_slots;
         S.last = *ctx->ctl_host;
     }
@@ -1588,7 +1591,8 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
             stats->global_relabel_launches = S.n_gr;
             stats->discharge_bytes = 40 * c.dverts + 13 * c.dslots + 16 * c.pushes + S.dense_rounds * (int64_t)n;
             stats->merge_bytes = 41 * c.mverts + 4 * c.mslots + 12 * c.pushes + S.dense_rounds * (int64_t)n;
-            stats->global_relabel_bytes = 12 * (c.gslots + c.hslots + S.td_slots) + S.grs * 9 * (int64_t)n +
+            stats->global_relabel_bytes = 12 * (c.gslots + c.hslots) + (S.st.hr ? 8 : 16) * S.td_slots +
+                                          S.grs * (9 * (int64_t)n + (S.st.hr ? 16 : 0) * (int64_t)S.g.slots) +
                                           S.bu_levels * 4 * (int64_t)n;
             for (int k = 0; k < MF_K_COUNT; k++) {
                 stats->kernel_ms[k] = S.kms[k];
