@@ -85,6 +85,26 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
+def copy_bandwidth_gbs(dev, mib: int = 2048, reps: int = 10) -> float:
+    """Device-to-device copy bandwidth on this GPU (torch's copy kernel over
+    `mib` MiB, read and written), the achievable streaming rate beside the
+    nominal peak."""
+    import torch
+    src = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    gbs = 2 * reps * (mib << 20) / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_model() -> str:
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
@@ -286,6 +306,66 @@ def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs:
             "oracle_checked_instances": len(checked), "wall_s": time.perf_counter() - t_all}
 
 
+def _changed_caps(cap, flow, frac: float, rng):
+    """New capacities on a random `frac` of the slots that carry capacity:
+    half raised by U{1..40}, half cut by U{1..40} but never below the slot's
+    flow in the last solve (so that the kept flow stays feasible)."""
+    import numpy as np
+    new = cap.copy()
+    cand = np.flatnonzero(cap > 0)
+    pick = rng.choice(cand, size=max(2, int(frac * cand.size)), replace=False)
+    up, down = pick[: pick.size // 2], pick[pick.size // 2:]
+    new[up] += rng.integers(1, 41, size=up.size, dtype=np.int32)
+    slack = cap[down] - np.maximum(flow[down], 0)
+    new[down] -= np.minimum(rng.integers(1, 41, size=down.size, dtype=np.int32), slack)
+    return new
+
+
+def resolve_leg(name: str, fracs=(0.001, 0.01, 0.1), seed: int = 11) -> dict:
+    """Served re-solves of a resident graph against cold requests of the
+    same graph: the graph is registered once (mf_server_register_graph);
+    each step changes a random fraction of the capacities and submits them
+    both as a re-solve of the resident graph (mf_server_submit_caps, which
+    resumes from the flow the server kept) and as a new request carrying the
+    whole graph (mf_server_submit).  Latency is the server's, from submit to
+    completion."""
+    import dataclasses
+    import numpy as np
+    import paper_1507_01926_amd as mf
+    from workloads import make_config
+    g = make_config(name)
+    ctx = mf.Context(0)
+    sc, sc_from = pick_schedule("cache", name, g, ctx, 0)
+    opt = mf.options(**sc)
+    srv = mf.Server(ctx, hbm_budget_bytes=64 << 30)
+    rng = np.random.default_rng(seed)
+    gid = srv.register_graph(g)
+    first = srv.wait(srv.submit_caps(gid, g.cap, opt), 600000)
+    cold0 = srv.wait(srv.submit(g, opt), 600000)
+    assert first["value"] == cold0["value"]
+    steps, cap, flow = [], g.cap, first["flow"]
+    for frac in fracs:
+        cap = _changed_caps(cap, flow, frac, rng)
+        warm = srv.wait(srv.submit_caps(gid, cap, opt), 600000)
+        cold = srv.wait(srv.submit(dataclasses.replace(g, cap=cap), opt), 600000)
+        assert warm["value"] == cold["value"] and warm["cut_capacity"] == cold["cut_capacity"]
+        steps.append({"changed_fraction": frac, "value": warm["value"], "resumed": bool(warm["resumed"]),
+                      "resolve_ms": warm["ms_latency"], "cold_request_ms": cold["ms_latency"],
+                      "resolve_rounds": [warm["rounds"], warm["rounds2"]],
+                      "cold_rounds": [cold["rounds"], cold["rounds2"]]})
+        flow = warm["flow"]
+        print(f"[bench] resolve {name} {frac}: {warm['ms_latency']:.1f} ms resumed, "
+              f"{cold['ms_latency']:.1f} ms cold", file=sys.stderr, flush=True)
+    srv.release_graph(gid)
+    srv.close()
+    ctx.close()
+    return {"workload": WORKLOADS[name], "schedule": sc, "schedule_from": sc_from,
+            "first_resident_solve_ms": first["ms_latency"], "cold_request_ms": cold0["ms_latency"],
+            "steps": steps,
+            "note": "each step raises half of the changed slots by U{1..40} and cuts the other half by "
+                    "U{1..40}, never below the slot's flow; steps follow one another on the same resident graph"}
+
+
 def schedule_options(g, knobs: dict) -> dict:
     thr = 12 * g.n + 2 * g.slots
     return dict(gr_round_charge=max(1, thr // knobs["round_divisor"]) if knobs.get("round_divisor") else 0,
@@ -371,6 +451,8 @@ def main():
                     help="instances per mf_batch_solve call of the closed-loop stream")
     ap.add_argument("--stream-oracle-every", type=int, default=64,
                     help="check every k-th stream instance (up to 2e5 vertices) against the CPU oracle")
+    ap.add_argument("--resolve", default="",
+                    help="workload of a served re-solve leg (resident graph, capacity changes; '' = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the solves, copy a buffer of this size on the device (a dispatch of known "
                          "traffic that scales the HBM counters of a profiler run)")
@@ -402,6 +484,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # (not in a counter run: its copies would be taken for the probe's)
+    copy_gbs = copy_bandwidth_gbs(dev) if args.copy_probe_mib == 0 else None
     print(f"[bench] warmup x{args.warmup}, timing x{args.steps}", file=sys.stderr, flush=True)
     T = time_solves(dg, g, opt, flow, side, args.steps, args.warmup, not args.persistent, mf)
     dt, runs, kernels, table = T["dt"], T["runs"], T["kernels"], T["table"]
@@ -460,7 +544,8 @@ def main():
                      "launches_per_step": launches_k / args.steps,
                      "alg_bytes_per_launch": bytes_k / max(1, launches_k),
                      "avg_launch_us": 1e3 * avg_launch_ms,
-                     "launches_timed": timed_k},
+                     "launches_timed": timed_k,
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None},
         "solve": {"value": r0["value"], "cut_capacity": r0["cut_capacity"],
                   "value_equals_cut": r0["value"] == r0["cut_capacity"],
                   "rounds": r0["rounds"], "rounds_phase2": r0["rounds2"],
@@ -504,6 +589,9 @@ def main():
         print(f"[bench] stream leg x{args.stream}", file=sys.stderr, flush=True)
         line["stream"] = stream_leg(args.stream, args.stream_nmax, "seeded", chunk=args.stream_chunk,
                                     oracle_every=args.stream_oracle_every)
+    if args.resolve:
+        print(f"[bench] served re-solve leg on {args.resolve}", file=sys.stderr, flush=True)
+        line["resolve"] = resolve_leg(args.resolve)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline_leg(args.workload)

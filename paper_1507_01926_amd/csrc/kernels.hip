@@ -283,6 +283,10 @@ __global__ void k_gr_init(GraphView g, StateView st, int sink)
 // frontier size to gr_found, from which the host derives the vertices a batch
 // of levels labelled.
 //
+// With packed heads the level claims an open neighbour by compare-and-swap
+// straight away, without reading its label first: a failed swap costs what
+// the read would, and the chain of dependent loads gets one link shorter.
+//
 // Flags: TD_TRACK_DEG sums the slots of the claimed vertices (the
 // direction choice on graphs with hubs), TD_EAGER reads the reverse residual
 // of every slot together with the neighbour's label instead of after it,
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(256) void k_gr_td(GraphView g, StateView st, int le
                     if (st.hr) {
                         const int x = st.hr[a];
                         w = x & 0x7fffffff;
-                        open = x < 0 && st.d[w] == g.n;
+                        open = x < 0;
                     } else if (flags & TD_EAGER) {
                         w = g.head[a];
                         const int r = st.res[g.rev[a]];

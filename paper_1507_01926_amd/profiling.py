@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the benchmark (profiles/*.txt).
 
-    python -m paper_1507_01926_amd.profiling kernels <trace dir> <title>
+    python -m paper_1507_01926_amd.profiling kernels <trace dir> <title> [<kernel> [<stride>]]
     python -m paper_1507_01926_amd.profiling traffic <fetch dir> <write dir> <kernel> <workload> <probe MiB>
 
 `kernels` condenses a `--kernel-trace --output-format csv` run into one
@@ -9,7 +9,8 @@ solve of the run (from its last k_init_state dispatch on).  `traffic` turns
 two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes per launch
 of one kernel over the last solve, each counter scaled by what it reads for
 the benchmark's device copy of known size (--copy-probe-mib: that many MiB
-read and written), in the key: value form that bench.py reads back.
+read and written, the last device copy before the solve), in the key: value
+form that bench.py reads back.
 """
 from __future__ import annotations
 
@@ -41,14 +42,35 @@ def _rows(root: str, suffix: str):
             yield from csv.DictReader(fh)
 
 
-def _last_solve(rows, start_key="Start_Timestamp"):
-    rows = sorted(rows, key=lambda r: int(r[start_key]))
+def _order(r) -> int:
+    """Launch order of a dispatch row (dispatch ids grow in launch order)."""
+    for k in ("Dispatch_Id", "Correlation_Id", "Start_Timestamp"):
+        if r.get(k):
+            return int(r[k])
+    return 0
+
+
+def _split_last_solve(rows):
+    """(rows before the last solve, rows of the last solve, solves seen): a
+    solve starts with its k_init_state dispatch."""
+    rows = sorted(rows, key=_order)
     starts = [i for i, r in enumerate(rows) if "k_init_state" in r["Kernel_Name"]]
-    return rows[starts[-1]:] if starts else rows, len(starts)
+    if not starts:
+        return [], rows, 0
+    return rows[:starts[-1]], rows[starts[-1]:], len(starts)
 
 
-def kernel_summary(trace_dir: str, title: str) -> str:
+def _last_solve(rows):
+    _, last, n = _split_last_solve(rows)
+    return last, n
+
+
+def kernel_summary(trace_dir: str, title: str, sampled: str = "", stride: int = 16) -> str:
+    """Per-kernel table of the last solve.  With `sampled`, also the average
+    duration of that kernel's launches 0, stride, 2*stride, ... of the solve
+    (the ones the benchmark brackets with HIP events) and of the others."""
     rows, solves = _last_solve(list(_rows(trace_dir, "kernel_trace.csv")))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     agg = collections.defaultdict(lambda: [0, 0])
     for r in rows:
         a = agg[r["Kernel_Name"]]
@@ -62,6 +84,14 @@ def kernel_summary(trace_dir: str, title: str) -> str:
            "# kernel" + " " * 62 + "calls   total_ms    avg_us    pct"]
     for k, (c, t) in sorted(agg.items(), key=lambda x: -x[1][1]):
         out.append(f"{k[:68]:68s} {c:8d} {t / 1e6:10.2f} {t / 1e3 / c:9.2f} {100 * t / 1e6 / busy:6.2f}")
+    if sampled:
+        d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows if sampled in r["Kernel_Name"]]
+        on = [x for i, x in enumerate(d) if i % stride == 0]
+        off = [x for i, x in enumerate(d) if i % stride != 0]
+        if on and off:
+            out.append(f"# {sampled}: launches 0, {stride}, {2 * stride}, ... of the solve (the ones the benchmark "
+                       f"brackets with HIP events): {len(on)} launches, avg {sum(on) / len(on) / 1e3:.2f} us; "
+                       f"the other {len(off)}: avg {sum(off) / len(off) / 1e3:.2f} us")
     return "\n".join(out) + "\n"
 
 
@@ -69,11 +99,12 @@ def _counter(root: str, name: str, kernel: str):
     """(per-dispatch values of `kernel` in the last solve, value of the copy
     probe) of counter `name`, in the counter's unit (KiB)."""
     rows = [r for r in _rows(root, "counter_collection.csv") if r.get("Counter_Name") == name]
-    probe = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-    last, _ = _last_solve(rows)
+    before, last, _ = _split_last_solve(rows)
+    # the probe copy is the last device copy launched before the solve
+    probe = [float(r["Counter_Value"]) for r in before if "copyBuffer" in r["Kernel_Name"]]
     vals = [float(r["Counter_Value"]) for r in last if kernel in r["Kernel_Name"]]
     sym = next((r["Kernel_Name"] for r in last if kernel in r["Kernel_Name"]), kernel)
-    return vals, (max(probe) if probe else None), sym
+    return vals, (probe[-1] if probe else None), sym
 
 
 def traffic_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, probe_mib: int,
@@ -109,7 +140,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, 
 if __name__ == "__main__":
     a = sys.argv[1:]
     if a[:1] == ["kernels"]:
-        sys.stdout.write(kernel_summary(a[1], a[2]))
+        sys.stdout.write(kernel_summary(a[1], a[2], *(a[3:4]), *(int(x) for x in a[4:5])))
     elif a[:1] == ["traffic"]:
         sys.stdout.write(traffic_summary(a[1], a[2], a[3], a[4], int(a[5]), a[6] if len(a) > 6 else ""))
     else:

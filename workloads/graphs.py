@@ -56,6 +56,22 @@ class Graph:
         return np.repeat(np.arange(self.n, dtype=np.int32), np.diff(self.off))
 
 
+def _stable_order(keys: np.ndarray) -> np.ndarray:
+    """np.argsort(keys, kind="stable") for non-negative int32 keys.  Keys in
+    a few sorted runs (grids, layered graphs) go to numpy's merge sort, which
+    takes such runs in linear time; scattered keys (R-MAT) take two 16-bit
+    radix passes (numpy sorts 16-bit keys by radix).  Both give the same
+    order: a stable sort's result is unique."""
+    if keys.shape[0] < (1 << 16) or np.count_nonzero(keys[1:] < keys[:-1]) < keys.shape[0] // 64:
+        return np.argsort(keys, kind="stable")
+    lo = (keys & 0xFFFF).astype(np.uint16)
+    o1 = np.argsort(lo, kind="stable")
+    del lo
+    hi = (keys >> 16).astype(np.uint16)[o1]
+    o2 = np.argsort(hi, kind="stable")
+    return o1[o2]
+
+
 def from_pairs(n, u, v, cap_uv, cap_vu, s, t, m_arcs, family="", params=None) -> Graph:
     """Build the CSR-pair arrays from a list of slot pairs.
 
@@ -71,7 +87,7 @@ def from_pairs(n, u, v, cap_uv, cap_vu, s, t, m_arcs, family="", params=None) ->
     head = np.concatenate([v, u])
     cap = np.concatenate([np.asarray(cap_uv, dtype=np.int32), np.asarray(cap_vu, dtype=np.int32)])
     del u, v
-    order = np.argsort(tail, kind="stable")
+    order = _stable_order(tail)
     cnt = np.bincount(tail, minlength=n)
     del tail
     pos = np.empty(2 * P, dtype=np.int64)
@@ -290,16 +306,22 @@ def rmat(scale, seed, edge_factor=16, a=0.57, b=0.19, c=0.19, top_frac=0.01) -> 
     rng = np.random.default_rng(seed)
     N = 1 << scale
     M = edge_factor * N
-    u = np.zeros(M, dtype=np.int64)
-    v = np.zeros(M, dtype=np.int64)
+    u = np.zeros(M, dtype=np.int32)
+    v = np.zeros(M, dtype=np.int32)
     ab, abc = a + b, a + b + c
+    # one bit of each endpoint per level: the quadrant q = [r >= a] + [r >=
+    # a+b] + [r >= a+b+c] of a uniform r (a, b, c, d in that order) gives
+    # the tail's bit (q >= 2) and the head's bit (q odd)
     for _ in range(scale):
         r = rng.random(M)
-        ubit = r >= ab
-        vbit = ((r >= a) & (r < ab)) | (r >= abc)
-        u = (u << 1) | ubit
-        v = (v << 1) | vbit
-        del r, ubit, vbit
+        q = (r >= a).view(np.uint8) + (r >= ab).view(np.uint8)
+        q += (r >= abc).view(np.uint8)
+        del r
+        u <<= 1
+        u |= q >> 1
+        v <<= 1
+        v |= q & 1
+        del q
     perm = rng.permutation(N).astype(np.int64)
     u = perm[u]
     v = perm[v]
