@@ -182,7 +182,7 @@ def _instances(count: int, n_hi: float, procs: int, ahead: int = 96):
 
 
 def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs: int = 0,
-               oracle_every: int = 0) -> dict:
+               oracle_every: int = 0, route: int = 0) -> dict:
     """Batched and served forms on a stream of `count` instances (family
     uniform over the five generator rules, n log-uniform in [1e3, n_hi]),
     with the lane knob from the autotuner, next to the plain solver run one
@@ -190,14 +190,22 @@ def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs:
     of worker processes ahead of their use; the closed-loop batched form
     takes them in chunks of `chunk` (each chunk one mf_batch_solve call, the
     chunks one after another), the served form at their Poisson arrival
-    times (a request waits for its instance to be generated if the pool
-    falls behind: its latency counts from its actual submission)."""
+    times.  A stream whose arrays fit in a few GB of host memory (n_hi up to
+    2e5) is generated once and replayed in every leg; a larger one is
+    generated again for each leg, and a request then waits for its instance
+    if the pool falls behind (its latency counts from its actual submission,
+    and requests_submitted_late counts such requests)."""
     import numpy as np
     import paper_1507_01926_amd as mf
     from paper_1507_01926_amd.autotune import Autotuner, bucket_of
     from workloads import stream_arrivals
 
     procs = procs or min(15, max(1, (os.cpu_count() or 2) - 1))
+    held = list(_instances(count, n_hi, procs)) if n_hi <= 2e5 else None
+
+    def source():
+        return iter(held) if held is not None else _instances(count, n_hi, procs)
+
     ctx = mf.Context(0)
     tuner = Autotuner(ctx, cache_path=None)
     t_all = time.perf_counter()
@@ -224,7 +232,7 @@ def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs:
             t0 = time.perf_counter()
             tuner.tune(fresh, mode="batch", reps=1, round_divisors=(0, 128, 32))
             tune_s += time.perf_counter() - t0
-        opts = [tuner.options_for(g, "batch") for g in graphs]
+        opts = [tuner.options_for(g, "batch", batch_grid_slots=route) for g in graphs]
         t0 = time.perf_counter()
         res, _ = mf.batch_solve(ctx, graphs, opts=opts, want_flow=False, want_side=False)
         dt = time.perf_counter() - t0
@@ -239,7 +247,7 @@ def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs:
             plain_ms.append(1e3 * (time.perf_counter() - t1))
             plain_vals.append(pr["value"])
 
-    for i, g in _instances(count, n_hi, procs):
+    for i, g in source():
         arcs += g.m_arcs
         fam[g.family] = fam.get(g.family, 0) + 1
         if oracle_every and i % oracle_every == 0 and g.n <= 2e5:
@@ -270,13 +278,13 @@ def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs:
         srv = mf.Server(ctx, hbm_budget_bytes=64 << 30)
         tickets, submit_late = [], 0
         t_start = time.perf_counter()
-        for i, g in _instances(count, n_hi, procs):
+        for i, g in source():
             delay = arr[i] - (time.perf_counter() - t_start)
             if delay > 0:
                 time.sleep(delay)
             elif delay < -0.005:
                 submit_late += 1
-            tickets.append(srv.submit(g, tuner.options_for(g, "batch"), want_flow=False))
+            tickets.append(srv.submit(g, tuner.options_for(g, "batch", batch_grid_slots=route), want_flow=False))
             if i % 512 == 511:
                 print(f"[bench] stream served {frac}x: {i + 1} submitted", file=sys.stderr, flush=True)
         out = [srv.wait(t, 1800000) for t in tickets]
@@ -298,9 +306,10 @@ def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs:
     ctx.close()
     return {"stream": f"{count} instances, n log-uniform in [1e3, {n_hi:.0e}], families uniform over "
                       f"the five generator rules ({seed_note}); instances above "
-                      f"262,144 slots run on "
+                      f"{route or mf.MF_BATCH_GRID_SLOTS:,} slots run on "
                       f"the grid-wide kernels in both forms",
             "families": fam, "arcs_total": arcs, "generator_processes": procs,
+            "instances_generated": "once, held in host memory" if held is not None else "again for every leg",
             "autotune_s": tune_s, "autotuned_buckets": len(tuned), "batched": batched, "served": served,
             "plain_one_at_a_time_solves_per_s": count / plain_total_s,
             "oracle_checked_instances": len(checked), "wall_s": time.perf_counter() - t_all}
@@ -451,6 +460,9 @@ def main():
                     help="instances per mf_batch_solve call of the closed-loop stream")
     ap.add_argument("--stream-oracle-every", type=int, default=64,
                     help="check every k-th stream instance (up to 2e5 vertices) against the CPU oracle")
+    ap.add_argument("--route-slots", type=int, default=0,
+                    help="stream leg: instances above this many slots go to the grid-wide kernels "
+                         "(0 = the library's default)")
     ap.add_argument("--resolve", default="",
                     help="workload of a served re-solve leg (resident graph, capacity changes; '' = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -588,7 +600,7 @@ def main():
     if args.stream > 0:
         print(f"[bench] stream leg x{args.stream}", file=sys.stderr, flush=True)
         line["stream"] = stream_leg(args.stream, args.stream_nmax, "seeded", chunk=args.stream_chunk,
-                                    oracle_every=args.stream_oracle_every)
+                                    oracle_every=args.stream_oracle_every, route=args.route_slots)
     if args.resolve:
         print(f"[bench] served re-solve leg on {args.resolve}", file=sys.stderr, flush=True)
         line["resolve"] = resolve_leg(args.resolve)

@@ -745,7 +745,8 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
     int level = 0;
     // Top-down levels launched per readback: 1 while the frontier grows
     // fast (the grid and the choice of a bottom-up level follow its size),
-    // doubling up to 32 while it stays within a factor 2 of the last one.
+    // doubling up to a cap of 32 to 128 while it stays within a factor 2 of
+    // the last one.
     int batch = 1;
     bool have_list = true;
     int32_t *qin = S.st.Q, *qout = S.st.Q2;
@@ -772,9 +773,9 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             // launches, with their kinds for the profile; events lev[2i] and
             // lev[2i+1] bracket launch i
             int nl = 0;
-            int kinds[2 * 32];
+            int kinds[2 * 128];
             if (S.profile) {
-                mf_status est = batch_events(ctx, 4 * 32);
+                mf_status est = batch_events(ctx, 4 * 128);
                 if (est != MF_OK) return est;
             }
             const int tdf = td_flags(hub_later, nq);
@@ -823,7 +824,11 @@ static mf_status global_relabel(Solve &S, int sink, int other, PhaseStats &ps, i
             unexplored = S.g.slots - deg_sink - c.gr_found_deg;
             fdeg = ended ? 0 : c.fdeg[(level + K) % 3];
             level += ran;
-            batch = nq_next > 2 * nq ? 1 : std::min(32, 2 * batch);
+            // the cap grows with the depth reached (32 up to level 128, 128 from
+            // level 512): a deep search saves readbacks, and a shallow one
+            // launches few empty levels after its frontier runs out
+            const int cap = (int)std::min<int64_t>(128, std::max<int64_t>(32, level / 4));
+            batch = nq_next > 2 * nq ? 1 : std::min(cap, 2 * batch);
             nq = nq_next;
             continue;
         }
