@@ -130,7 +130,9 @@ typedef struct {
                                   rounds and per-slot flow differ.  Grid-wide kernels only
                                   (small graphs use them too); not in the batched and served
                                   forms, with MF_PERSISTENT or without allocation (MF_EINVAL) */
-#define MF_BATCH_GRID_SLOTS 524288
+/* Batched and served forms: instances with more slots than this (by default)
+ * are solved by the grid-wide kernels instead of one workgroup each. */
+#define MF_BATCH_GRID_SLOTS 2097152
 #define MF_SMALL_N      8192
 #define MF_SMALL_SLOTS  16384
 
@@ -173,7 +175,8 @@ typedef struct {
                                     vertices, consecutive rounds run inside one workgroup with block
                                     barriers instead of launches per round (the same rounds, so the
                                     same results); 0 = automatic (256), negative = never.  Not used
-                                    on graphs with hub vertices or with MF_CHECK_INVARIANTS */
+                                    on graphs with hub vertices, with MF_CHECK_INVARIANTS or with
+                                    MF_GAP_RELABEL */
     int32_t grid_workers;        /* batched form: instances above the routing size are solved by this
                                     many host threads at once, each with a stream of its own (0 = 4);
                                     the first instance's value counts for the batch */

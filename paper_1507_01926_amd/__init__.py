@@ -28,7 +28,7 @@ MF_SIMPLE_ROUNDS = 0x10
 MF_WARM_START = 0x20
 MF_CHECK_INVARIANTS = 0x40
 MF_GAP_RELABEL = 0x80
-MF_BATCH_GRID_SLOTS = 524288      # default routing size of the batched and served forms
+MF_BATCH_GRID_SLOTS = 2097152     # default routing size of the batched and served forms
 
 
 class MaxflowError(RuntimeError):

@@ -78,8 +78,8 @@ def test_batch_large_instances_match_oracle(ctx, large):
 
 
 def test_batch_default_routing(ctx, large):
-    """With the default routing size, instances above it (R-MAT here) go to
-    the grid-wide kernels while the batch launch runs, the rest run in it."""
+    """With the default routing size, instances above it go to the grid-wide
+    kernels while the batch launch runs, the rest run in it."""
     import paper_1507_01926_amd as mf
     graphs = [g for g, _ in large]
     res, _ = mf.batch_solve(ctx, graphs)
