@@ -287,7 +287,11 @@ def stream_leg(count: int, n_hi: float, seed_note: str, chunk: int = 256, procs:
             tickets.append(srv.submit(g, tuner.options_for(g, "batch", batch_grid_slots=route), want_flow=False))
             if i % 512 == 511:
                 print(f"[bench] stream served {frac}x: {i + 1} submitted", file=sys.stderr, flush=True)
-        out = [srv.wait(t, 1800000) for t in tickets]
+        out = []
+        for j, t in enumerate(tickets):
+            out.append(srv.wait(t, 1800000))
+            if j % 512 == 511:
+                print(f"[bench] stream served {frac}x: {j + 1} done", file=sys.stderr, flush=True)
         span = time.perf_counter() - t_start
         st = srv.stats()
         srv.close()
