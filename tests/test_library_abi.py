@@ -145,14 +145,23 @@ def test_bench_traffic_only_for_the_profiled_sources(monkeypatch):
     kernel only while the profile was taken on the current HIP sources."""
     sys.path.insert(0, ROOT)
     import bench
-    path = os.path.join(ROOT, "profiles", "k_gr_td_c2_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "k_gr_td_c3_traffic.txt")
     recorded = [l.split(":", 1)[1].strip() for l in open(path) if l.startswith("source_sha256:")][0]
     per_launch = [float(l.split(":", 1)[1]) for l in open(path) if l.startswith("hbm_bytes_per_launch:")][0]
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: recorded)
-    assert bench.measured_traffic("k_gr_td", "c2") == per_launch
-    assert bench.measured_traffic("k_gr_td", "c3") is None     # no profile for that workload
+    assert bench.measured_traffic("k_gr_td", "c3") == per_launch
+    assert bench.measured_traffic("k_gr_td", "c2") is None     # no profile for that workload
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 64)
-    assert bench.measured_traffic("k_gr_td", "c2") is None     # sources changed since the counters
+    assert bench.measured_traffic("k_gr_td", "c3") is None     # sources changed since the counters
+
+
+def test_committed_traffic_profile_matches_the_sources():
+    """The committed k_gr_td traffic summary of the headline workload was
+    taken on the HIP sources as they stand."""
+    from paper_1507_01926_amd.profiling import source_sha
+    path = os.path.join(ROOT, "profiles", "k_gr_td_c3_traffic.txt")
+    recorded = [l.split(":", 1)[1].strip() for l in open(path) if l.startswith("source_sha256:")][0]
+    assert recorded == source_sha()
 
 
 def test_bench_fixed_schedule():
