@@ -507,7 +507,7 @@ __global__ void k_gr_rebuild(GraphView g, StateView st, int sink, int other)
 
 // List mode: the working set is A[0 .. na).  In a batch of speculative rounds
 // a round after the one that stopped the batch does nothing.
-template <int G>
+template <int G, bool TWO>
 __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView st, RoundParams p)
 {
     if (st.ctl->batch_stop) return;
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView s
             wave_append(gl == 0, v, st.H, &st.ctl->nhd);
             continue;
         }
-        discharge_vertex<G, false>(g, st, p, v, gl, acc, &stage);
+        discharge_vertex<G, false, TWO>(g, st, p, v, gl, acc, &stage);
     }
     stage_flush_owner(stage, st.C, &st.ctl->nc, st.owner);
     discharge_flush(st, p, acc);
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256) void k_discharge_list(GraphView g, StateView s
 // active vertices that cluster in one region of the graph still spread over
 // the whole grid.  Pushes mark their heads in touched[] instead of appending
 // candidates.
-template <int G>
+template <int G, bool TWO>
 __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView st, RoundParams p)
 {
     if (st.ctl->batch_stop) return;
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(256) void k_discharge_dense(GraphView g, StateView 
             wave_append(gl == 0, v, st.H, &st.ctl->nhd);
             continue;
         }
-        discharge_vertex<G, true>(g, st, p, v, gl, acc);
+        discharge_vertex<G, true, TWO>(g, st, p, v, gl, acc);
     }
     discharge_flush(st, p, acc);
 }
@@ -1043,11 +1043,22 @@ void launch_rounds_block(int G, GraphView g, StateView st, RoundParams p, int ot
 }
 
 void launch_discharge(int G, bool dense, GraphView g, StateView st, RoundParams p, int grid, hipStream_t s,
-                      KEv ev)
+                      KEv ev, bool two)
 {
-#define C_(X)                                                      \
-    if (dense) MF_LAUNCH((k_discharge_dense<X>), grid, s, ev, g, st, p); \
-    else MF_LAUNCH((k_discharge_list<X>), grid, s, ev, g, st, p)
+    // the two-chunk variants exist for 4 and 8 lanes
+    if (two && G == 4) {
+        if (dense) MF_LAUNCH((k_discharge_dense<4, true>), grid, s, ev, g, st, p);
+        else MF_LAUNCH((k_discharge_list<4, true>), grid, s, ev, g, st, p);
+        return;
+    }
+    if (two && G == 8) {
+        if (dense) MF_LAUNCH((k_discharge_dense<8, true>), grid, s, ev, g, st, p);
+        else MF_LAUNCH((k_discharge_list<8, true>), grid, s, ev, g, st, p);
+        return;
+    }
+#define C_(X)                                                             \
+    if (dense) MF_LAUNCH((k_discharge_dense<X, false>), grid, s, ev, g, st, p); \
+    else MF_LAUNCH((k_discharge_list<X, false>), grid, s, ev, g, st, p)
     MF_DISPATCH_G(G, C_)
 #undef C_
 }

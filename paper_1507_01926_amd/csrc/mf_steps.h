@@ -66,8 +66,10 @@ struct DisAcc {
 };
 
 // Full discharge of one vertex v by a group of G lanes (the loop body of
-// Listing 1 for one element of the working set).
-template <int G, bool DENSE>
+// Listing 1 for one element of the working set).  TWO: vertices of up to 2G
+// slots keep both chunks in registers across passes (more registers per
+// lane; the host uses it for graphs whose vertices all fit).
+template <int G, bool DENSE, bool TWO = false>
 __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &st, const RoundParams &p,
                                                  int v, int gl, DisAcc &acc, Stage *sg = nullptr)
 {
@@ -113,6 +115,60 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
             if (p.simple) break;                              // one relabel per round
         }
         if (dirty) st.res[a] = r;
+    } else if (TWO && deg <= 2 * G) {
+        // Two chunks, both kept in registers across passes (slot a0 of the
+        // first, a1 of the second; lanes past the end hold r = 0).  Only v
+        // writes these residuals during the round and the labels and
+        // activity it reads are the round's snapshot, so the registers stay
+        // current; each pass visits the chunks in slot order as the loop
+        // below does.
+        const int a0 = beg + gl, a1 = beg + G + gl;
+        int r0 = st.res[a0], w0 = -1, dw0 = 0;
+        int r1 = 0, w1 = -1, dw1 = 0;
+        bool aw0 = false, aw1 = false;
+        if (r0 > 0) {
+            w0 = g.head[a0];
+            dw0 = st.d[w0];
+            aw0 = st.act[w0] != 0;
+        }
+        if (a1 < end) {
+            r1 = st.res[a1];
+            if (r1 > 0) {
+                w1 = g.head[a1];
+                dw1 = st.d[w1];
+                aw1 = st.act[w1] != 0;
+            }
+        }
+        bool dirty0 = false, dirty1 = false;
+        while (el > 0) {
+            int cand = n;
+            bool lose;
+            if (gl == 0) acc.scans += G;
+            if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a0, r0, w0, dw0, aw0, el, lose, acc.pushes, p.sink,
+                                     acc.to_sink, p.simple, sg) > 0)
+                dirty0 = true;
+            if (el == 0) break;
+            if (r0 > 0 && dw0 >= dp) cand = dw0 + 1;
+            int sk = lose ? 1 : 0;
+            if (gl == 0) acc.scans += deg - G;
+            if (chunk_pass<G, DENSE>(g, st, v, dv, dp, gl, a1, r1, w1, dw1, aw1, el, lose, acc.pushes, p.sink,
+                                     acc.to_sink, p.simple, sg) > 0)
+                dirty1 = true;
+            if (el == 0) break;
+            if (r1 > 0 && dw1 >= dp && dw1 + 1 < cand) cand = dw1 + 1;
+            sk |= lose ? 1 : 0;
+            const int nl = group_min<G>(cand);
+            if (group_or<G>(sk)) break;
+            dp = nl < n ? nl : n;
+            if (gl == 0) {
+                acc.work += deg + p.beta;
+                acc.relabels++;
+            }
+            if (dp >= n) break;
+            if (p.simple) break;
+        }
+        if (dirty0) st.res[a0] = r0;
+        if (dirty1) st.res[a1] = r1;
     } else {
         while (el > 0) {
             int cand = n;

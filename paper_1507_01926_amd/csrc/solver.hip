@@ -37,7 +37,7 @@ void launch_discharge_hubs(bool dense, GraphView g, StateView st, RoundParams p,
 void launch_merge_hubs(bool dense, GraphView g, StateView st, int sink, int other, int grid, hipStream_t s,
                        KEv ev = KEv());
 void launch_discharge(int G, bool dense, GraphView g, StateView st, RoundParams p, int grid, hipStream_t s,
-                      KEv ev = KEv());
+                      KEv ev = KEv(), bool two = false);
 void launch_merge(int G, bool dense, GraphView g, StateView st, int sink, int other, int hubd, int grid,
                   hipStream_t s, KEv ev = KEv());
 void launch_gr_td(int G, GraphView g, StateView st, int level, int sink, int other, const int32_t *qin,
@@ -600,6 +600,11 @@ struct Solve {
     bool check;                // MF_CHECK_INVARIANTS: state checks after every round and global relabel
     int block_small_max;       // working sets up to this size run their rounds in one workgroup (0 = never)
     bool gap;                  // MF_GAP_RELABEL: the gap rule after every round
+    // the discharge kernels that keep two chunks of slots in registers: used
+    // when every vertex other than s and t has more than G and at most 2G
+    // slots (the 3D grid at 4 lanes); they cost registers, and occupancy,
+    // that other graphs do not repay
+    bool two_chunks = false;
     bool fault_done = false;   // the check_fault_round test hook has fired
     // profiling accumulators
     double ms_dis = 0, ms_mer = 0, ms_gr = 0, ms_phase = 0;
@@ -1021,7 +1026,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                 const int q = 8 * j;
                 if (j == 0) launch_round_begin(ctx->ctl, 1, ctx->stream);
                 launch_discharge(S.G, false, S.g, sj, rp, dgrid, ctx->stream,
-                       kev(S, MF_K_DISCHARGE_LIST, e, q + 0));
+                       kev(S, MF_K_DISCHARGE_LIST, e, q + 0), S.two_chunks);
                 if (S.hub_kernels) {
                     launch_discharge_hubs(false, S.g, sj, rp, S.hub_grid, ctx->stream,
                            kev(S, MF_K_DISCHARGE_HUB, e, q + 2));
@@ -1120,7 +1125,7 @@ static mf_status run_phase(Solve &S, int sink, int other, int64_t max_rounds, Ph
                        kev(S, MF_K_COMPACT, e, 0));
             }
             launch_discharge(S.G, true, S.g, sj, rp, dgrid, ctx->stream,
-                   kev(S, MF_K_DISCHARGE_DENSE, e, 2));
+                   kev(S, MF_K_DISCHARGE_DENSE, e, 2), S.two_chunks);
             if (S.hub_kernels) {
                 launch_discharge_hubs(true, S.g, sj, rp, S.hub_grid, ctx->stream,
                        kev(S, MF_K_DISCHARGE_HUB, e, 4));
@@ -1496,6 +1501,8 @@ static mf_status solve_uploaded(mf_context *ctx, mf_dgraph *dg, const mf_options
     S.st.gcand = S.gap ? w.gcand : nullptr;
     S.block_small_max = (o.block_round_max < 0 || S.check || S.hub_kernels || S.gap) ? 0
                         : (o.block_round_max > 0 ? o.block_round_max : 256);
+    S.two_chunks = (S.G == 4 || S.G == 8) && !S.hub_kernels && dg->maxdeg_inner > S.G &&
+                   dg->maxdeg_inner <= 2 * S.G;
     if (o.dense_threshold > 0) S.dense_threshold = o.dense_threshold;
 
     const int n = dg->n;
