@@ -89,8 +89,9 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
         bool aw = false;
         if (gl < deg) {
             r = st.res[a];
+            const int h = g.head[a];     // read beside the residual: one link fewer
             if (r > 0) {
-                w = g.head[a];
+                w = h;
                 dw = st.d[w];
                 aw = st.act[w] != 0;
             }
@@ -126,18 +127,18 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
         int r0 = st.res[a0], w0 = -1, dw0 = 0;
         int r1 = 0, w1 = -1, dw1 = 0;
         bool aw0 = false, aw1 = false;
+        const int h0 = g.head[a0];
+        const int h1 = a1 < end ? g.head[a1] : -1;
+        if (a1 < end) r1 = st.res[a1];
         if (r0 > 0) {
-            w0 = g.head[a0];
+            w0 = h0;
             dw0 = st.d[w0];
             aw0 = st.act[w0] != 0;
         }
-        if (a1 < end) {
-            r1 = st.res[a1];
-            if (r1 > 0) {
-                w1 = g.head[a1];
-                dw1 = st.d[w1];
-                aw1 = st.act[w1] != 0;
-            }
+        if (r1 > 0) {
+            w1 = h1;
+            dw1 = st.d[w1];
+            aw1 = st.act[w1] != 0;
         }
         bool dirty0 = false, dirty1 = false;
         while (el > 0) {
@@ -179,8 +180,9 @@ __device__ __forceinline__ void discharge_vertex(const GraphView &g, StateView &
                 bool aw = false;
                 if (a < end) {
                     r = st.res[a];
+                    const int h = g.head[a];
                     if (r > 0) {
-                        w = g.head[a];
+                        w = h;
                         dw = st.d[w];
                         aw = st.act[w] != 0;
                     }
