@@ -418,3 +418,26 @@ def test_gap_rule_leaves_no_gap(name, f):
     assert G["value"] == A["value"]
     assert (G["tstar"] == A["tstar"]).all()
     _cert_ok(g, G["flow"], G["tstar"])
+
+
+# ---------------------------------------------------------------- phase 2 (R17)
+
+@pytest.mark.parametrize("name,f", [("c1", 1), ("c2", 16), ("c3", 16), ("c4a", 64), ("c4b", 64)])
+def test_phase2_leaves_the_sink_side_alone(name, f):
+    """Phase 2 (returning the stranded excess to s, Sec. 2.1's second phase,
+    reading R17) runs over V minus T* and never changes the residual of a
+    slot with an end in T*: the preflow's flow on every such slot is the
+    final flow's, so the value and the minimum cut carry over unchanged.
+    After phase 2 every vertex other than s and t has zero excess."""
+    g = make_config(name, f)
+    P = oracle.sync_maxflow(g, preflow_only=True)
+    F = oracle.sync_maxflow(g)
+    assert (P["tstar"] == F["tstar"]).all() and P["value"] == F["value"]
+    tails = np.repeat(np.arange(g.n), np.diff(g.off))
+    touches = (F["tstar"][tails] == 1) | (F["tstar"][g.head] == 1)
+    assert touches.any() and (~touches).any()
+    assert (P["res"][touches] == F["res"][touches]).all()
+    inner = np.ones(g.n, bool)
+    inner[[g.s, g.t]] = False
+    assert (F["e"][inner] == 0).all()
+    assert (P["e"][inner] > 0).any()                   # phase 1 strands excess that phase 2 returns
