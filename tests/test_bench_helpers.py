@@ -39,3 +39,21 @@ def test_stream_instances_are_generated_in_order():
     for i, g in got:
         ref = stream_instance(i, n_hi=3e3)
         assert g.n == ref.n and (g.head == ref.head).all() and (g.cap == ref.cap).all()
+
+
+def test_schedule_cache_is_tuned_elsewhere_and_within_the_candidates():
+    """Every workload in the committed schedule cache was tuned on another
+    instance of its generator rule (a seed offset), never the benchmarked one,
+    and its schedule is one of the autotuner's candidates (the full-size GPU
+    tests check every candidate against the oracle's goldens)."""
+    import json
+    from paper_1507_01926_amd.autotune import SCHEDULE_CACHE, SCHEDULES
+    with open(SCHEDULE_CACHE) as fh:
+        cache = json.load(fh)
+    assert {"c2", "c3"} <= set(cache)
+    cands = {(rd, fd, lc) for rd, fd, lc in SCHEDULES}
+    for name, entry in cache.items():
+        assert "seed offset" in entry["tuned_on"] and "not the benchmarked instance" in entry["tuned_on"]
+        k = entry["knobs"]
+        assert (k["round_divisor"], k["freq_den"], k["level_charge"]) in cands, name
+        assert entry["ms"] == min(c["ms"] for c in entry["candidates"])
